@@ -1,0 +1,209 @@
+"""Literal pruning dual-tree k-NN on tiny inputs (test infrastructure only).
+
+The paper's meta-algorithm (Section "Overview"): a space tree (here the
+kd-tree of ``oracle.kdtree``), a pruning dual-tree traversal (Algorithm 1,
+depth first), the k-NN BaseCase (Algorithm 2) and the k-NN Score
+(Algorithm 3).  Nothing is blocked, fused or reordered; it exists to pin the
+reading of the bound B(N_q) and to show that pruning with it is exact.
+
+Traversal detail: Algorithm 1 recurses over C_q x C_r; for a kd-tree, whose
+points sit only in leaves, a childless node stands for itself in that
+product (the convention of Gray's AllNN, Algorithm 4), and the recursion
+stops when both nodes are leaves.  Children of the reference node are taken
+closer-first (Algorithm 4).
+
+Bounds (Section "k-Nearest Neighbor Search"):
+
+``B1``      max over the node's descendant points of D_p[k].
+``B``       the combined bound, safe reading: the four-way minimum of
+            B1(N_q), min_p D_p[k] + rho + lambda (rho = lambda at a kd-tree
+            leaf, and every descendant point lies in some leaf, so this is
+            min over descendants of D_p[k] + 2 lambda(N_q)), and B(Par(N_q)).
+            The printed child term B(N_c) + 2(lambda_q - lambda_c) is left
+            out: it is justified only when B(N_c) is attained by its
+            minimum-plus-2-lambda term, and the tests exhibit inputs where the
+            printed recursion falls below the largest true k-th distance.
+``printed`` the recursion exactly as printed, evaluated bottom-up, for
+            those tests only.
+``none``    never prune (the non-pruning traversal of the correctness
+            argument).
+
+Distances are FP64.  Algorithm 3 visits when d_min < B, i.e. prunes when
+d_min >= B.  That is safe for B1 (a point at exactly the current k-th
+distance is not a strict improvement for the BaseCase) but not for the
+minimum-plus-2-lambda term, whose triangle-inequality argument only
+guarantees k points at distance <= B, not yet found: with ties (a point at
+exactly that distance) the non-strict prune discards a true neighbour.  The
+default here is the strict prune d_min > B; ``strict=False`` gives the
+printed comparison, for the test that exhibits the difference.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import kdtree as _kd
+
+
+class DualTreeKNN:
+    def __init__(self, qpts, rpts, k, leaf_size=2, bound="B", exclude_self=False,
+                 strict=True):
+        self.q = np.asarray(qpts, np.float32).astype(np.float64)
+        self.r = np.asarray(rpts, np.float32).astype(np.float64)
+        self.k = k
+        self.bound = bound
+        self.exclude_self = exclude_self
+        self.strict = strict
+        self.tq = _kd.build(qpts, leaf_size)
+        self.tr = _kd.build(rpts, leaf_size)
+        n = self.q.shape[0]
+        self.D = np.full((n, k), np.inf)       # candidate distances, ascending
+        self.N = np.full((n, k), -1, np.int64)  # candidate indices
+        self.base_cases = 0
+        self.score_calls = 0
+        self.visited = set()
+
+    # --- tree helpers -------------------------------------------------------
+    def _is_leaf(self, t, node):
+        return node >= t["first_leaf"]
+
+    def _children(self, t, node):
+        return [] if self._is_leaf(t, node) else [2 * node + 1, 2 * node + 2]
+
+    def _points(self, t, node):
+        s, c = t["start"][node], t["count"][node]
+        return t["perm"][s:s + c]
+
+    def _held(self, t, node):
+        return self._points(t, node) if self._is_leaf(t, node) else np.empty(0, np.int64)
+
+    def _dmin(self, nq, nr):
+        """Lower bound on d_min: distance between the two boxes."""
+        tq, tr = self.tq, self.tr
+        if tq["count"][nq] == 0 or tr["count"][nr] == 0:
+            return math.inf
+        lo_q, hi_q = tq["lo"][nq].astype(np.float64), tq["hi"][nq].astype(np.float64)
+        lo_r, hi_r = tr["lo"][nr].astype(np.float64), tr["hi"][nr].astype(np.float64)
+        gap = np.maximum(0.0, np.maximum(lo_r - hi_q, lo_q - hi_r))
+        return float(np.sqrt((gap * gap).sum()))
+
+    # --- bounds -------------------------------------------------------------
+    def _kth(self, node):
+        return self.D[self._points(self.tq, node), self.k - 1]
+
+    def _B_safe(self, node, with_b2=True):
+        pts = self._kth(node)
+        if pts.size == 0:
+            return math.inf
+        b = pts.max()
+        if with_b2:
+            b = min(b, pts.min() + 2.0 * self.tq["lam"][node])
+        if node > 0:
+            b = min(b, self._B_safe((node - 1) // 2, with_b2))
+        return b
+
+    def _B_printed_up(self, node):
+        t = self.tq
+        if t["count"][node] == 0:
+            return math.inf
+        held = self.D[self._held(t, node), self.k - 1]
+        kids = [c for c in self._children(t, node) if t["count"][c] > 0]
+        kb = [self._B_printed_up(c) for c in kids]
+        lam = t["lam"][node]
+        rho = lam if self._is_leaf(t, node) else 0.0
+        maxes = ([held.max()] if held.size else []) + kb
+        terms = [max(maxes)]
+        if held.size:
+            terms.append(held.min() + rho + lam)
+        for c, b in zip(kids, kb):
+            terms.append(b + 2.0 * (lam - t["lam"][c]))
+        return min(terms)
+
+    def _B_printed(self, node):
+        b = self._B_printed_up(node)
+        if node > 0:
+            b = min(b, self._B_printed((node - 1) // 2))
+        return b
+
+    def bound_of(self, node):
+        if self.bound == "none":
+            return math.inf
+        if self.bound == "B1":
+            return self._B_safe(node, with_b2=False)
+        if self.bound == "B":
+            return self._B_safe(node, with_b2=True)
+        if self.bound == "printed":
+            return self._B_printed(node)
+        raise ValueError(self.bound)
+
+    # --- the three callbacks ------------------------------------------------
+    def score(self, nq, nr):
+        self.score_calls += 1
+        dmin = self._dmin(nq, nr)
+        b = self.bound_of(nq)
+        keep = dmin <= b if self.strict else dmin < b
+        return dmin if keep else math.inf
+
+    def base_case(self, iq, ir):
+        if self.exclude_self and iq == ir:
+            return math.inf
+        self.base_cases += 1
+        diff = self.q[iq] - self.r[ir]
+        d = math.sqrt(float(diff @ diff))
+        if d < self.D[iq, self.k - 1] and (iq, ir) not in self.visited:
+            self.visited.add((iq, ir))
+            row_d, row_n = self.D[iq], self.N[iq]
+            pos = int(np.searchsorted(row_d, d, side="right"))
+            row_d[pos + 1:] = row_d[pos:-1].copy()
+            row_n[pos + 1:] = row_n[pos:-1].copy()
+            row_d[pos], row_n[pos] = d, ir
+        return d
+
+    def traverse(self, nq=0, nr=0):
+        if self.score(nq, nr) == math.inf:
+            return
+        for iq in self._held(self.tq, nq):
+            for ir in self._held(self.tr, nr):
+                self.base_case(int(iq), int(ir))
+        cq = self._children(self.tq, nq) or [nq]
+        cr = self._children(self.tr, nr) or [nr]
+        if cq == [nq] and cr == [nr]:
+            return
+        for c in cq:
+            # closer reference child first
+            order = sorted(cr, key=lambda x: self._dmin(c, x))
+            for x in order:
+                self.traverse(c, x)
+
+    def run(self):
+        self.traverse(0, 0)
+        return self.N.copy(), self.D.copy()
+
+
+def printed_bound_bottom_up(tree, kth):
+    """The printed recursion for B(N) (without the parent term) evaluated
+    bottom-up from per-point k-th distances ``kth`` (indexed by original
+    row), together with the safe-reading value and the true requirement
+    max over descendants of kth, for every node."""
+    n_nodes, fl = tree["n_nodes"], tree["first_leaf"]
+    lam = tree["lam"]
+    printed = np.full(n_nodes, np.inf)
+    safe = np.full(n_nodes, np.inf)
+    need = np.full(n_nodes, -np.inf)
+    for node in range(n_nodes - 1, -1, -1):
+        s, c = tree["start"][node], tree["count"][node]
+        pts = kth[tree["perm"][s:s + c]]
+        if pts.size == 0:
+            continue
+        need[node] = pts.max()
+        safe[node] = min(pts.max(), pts.min() + 2.0 * lam[node])
+        if node >= fl:
+            printed[node] = min(pts.max(), pts.min() + 2.0 * lam[node])
+        else:
+            kids = [2 * node + 1, 2 * node + 2]
+            kb = [printed[x] for x in kids if tree["count"][x] > 0]
+            terms = [max(kb)] + [printed[x] + 2.0 * (lam[node] - lam[x])
+                                 for x in kids if tree["count"][x] > 0]
+            printed[node] = min(terms)
+    return printed, safe, need

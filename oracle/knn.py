@@ -1,0 +1,110 @@
+"""FP64 brute-force k-NN oracle (test infrastructure only).
+
+``knn(q, r, k, exclude_self)`` is the definition the dual-tree method reaches
+exactly (Section "k-Nearest Neighbor Search": the problem statement -- for
+each query the k nearest references and their distances, 0 < k < m -- and the
+brute-force remark that every pair is compared and the k smallest kept).  The
+work runs in ``knn_bruteforce.c`` (OpenMP); ``knn_numpy`` is the same
+definition in a few lines of numpy for tiny inputs.
+
+Ties are ordered by reference index; with ``exclude_self`` (query set equal to
+the reference set, the footnote to the k-NN BaseCase) reference i is skipped
+for query i by index identity.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+        lib = ctypes.CDLL(path)
+        i64, i32 = ctypes.c_int64, ctypes.c_int32
+        p = ctypes.c_void_p
+        lib.knn_oracle_bruteforce.argtypes = [p, i64, p, i64, i32, i32, i32, p, p]
+        lib.knn_oracle_bruteforce.restype = ctypes.c_int
+        lib.knn_oracle_bruteforce_rows.argtypes = [p, p, i64, p, i64, i32, i32, i32, p, p]
+        lib.knn_oracle_bruteforce_rows.restype = ctypes.c_int
+        lib.knn_oracle_pair_d2.argtypes = [p, p, i32, p, p, i64, p]
+        lib.knn_oracle_pair_d2.restype = ctypes.c_int
+        lib.knn_oracle_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def threads() -> int:
+    return int(_load().knn_oracle_threads())
+
+
+def knn(q, r, k: int, exclude_self: bool = False):
+    """All queries.  Returns (idx int64 [n,k], d2 float64 [n,k])."""
+    q, r = _f32(q), _f32(r)
+    n, d = q.shape
+    m = r.shape[0]
+    idx = np.empty((n, k), np.int64)
+    d2 = np.empty((n, k), np.float64)
+    rc = _load().knn_oracle_bruteforce(q.ctypes.data, n, r.ctypes.data, m, d, k,
+                                       int(bool(exclude_self)), idx.ctypes.data,
+                                       d2.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle: invalid arguments (need 0 < k < m)")
+    return idx, d2
+
+
+def knn_rows(q, rows, r, k: int, exclude_self: bool = False):
+    """Queries ``q[rows]`` only (rows are indices into q)."""
+    q, r = _f32(q), _f32(r)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    d = q.shape[1]
+    m = r.shape[0]
+    idx = np.empty((len(rows), k), np.int64)
+    d2 = np.empty((len(rows), k), np.float64)
+    rc = _load().knn_oracle_bruteforce_rows(q.ctypes.data, rows.ctypes.data, len(rows),
+                                            r.ctypes.data, m, d, k,
+                                            int(bool(exclude_self)), idx.ctypes.data,
+                                            d2.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle: invalid arguments (need 0 < k < m)")
+    return idx, d2
+
+
+def pair_d2(q, r, qi, ri):
+    """FP64 squared distance of explicit pairs (q[qi[t]], r[ri[t]])."""
+    q, r = _f32(q), _f32(r)
+    qi = np.ascontiguousarray(qi, dtype=np.int64).ravel()
+    ri = np.ascontiguousarray(ri, dtype=np.int64).ravel()
+    out = np.empty(qi.shape[0], np.float64)
+    rc = _load().knn_oracle_pair_d2(q.ctypes.data, r.ctypes.data, q.shape[1],
+                                    qi.ctypes.data, ri.ctypes.data, qi.shape[0],
+                                    out.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle: invalid arguments")
+    return out
+
+
+def knn_numpy(q, r, k: int, exclude_self: bool = False):
+    """The same definition in numpy (tiny inputs): full distance matrix, then
+    a stable sort on (distance, index)."""
+    q = np.asarray(q, np.float32).astype(np.float64)
+    r = np.asarray(r, np.float32).astype(np.float64)
+    diff = q[:, None, :] - r[None, :, :]
+    d2 = np.einsum("ijk,ijk->ij", diff, diff)
+    if exclude_self:
+        np.fill_diagonal(d2, np.inf)
+    order = np.argsort(d2, axis=1, kind="stable")[:, :k]
+    return order.astype(np.int64), np.take_along_axis(d2, order, axis=1)

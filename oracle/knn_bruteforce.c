@@ -1,0 +1,158 @@
+/*
+ * Oracle (test infrastructure only): exact k-nearest-neighbour search by brute
+ * force, in FP64, on the CPU.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this library.  The GPU search never calls it and shares no code,
+ * header or table with it.
+ *
+ * What it computes (Section "k-Nearest Neighbor Search", problem statement
+ * and brute-force remark): for every query q in S_q (n rows of d FP32
+ * values) it compares q with every reference r in S_r (m rows) and keeps the
+ * k smallest distances, in ascending order.  Distances are Euclidean
+ * (Section "Space Trees", minimum-distance definition, which uses the 2-norm).
+ *
+ * Readings where the paper is silent:
+ *   - coordinates are FP32 inputs, upcast to FP64 before subtraction, so the
+ *     squared distance is computed with ~1e-16 relative error;
+ *   - equal distances are ordered by reference index (lower first);
+ *   - with exclude_self != 0 (query set identical to reference set, footnote
+ *     to the k-NN BaseCase), reference i is skipped for query i, by index
+ *     identity only: an exact duplicate with another index is kept.
+ *
+ * Outputs: idx_out[i*k + j] = reference row of the j-th neighbour of query i,
+ * d2_out[i*k + j] = its squared distance (FP64).  Returns 0 on success, -1
+ * on invalid arguments (0 < k < m violated, or k > m - 1 with exclusion).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <math.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int knn_oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* lexicographic order on (squared distance, reference index) */
+static int before(double da, int64_t ia, double db, int64_t ib)
+{
+    return (da < db) || (da == db && ia < ib);
+}
+
+int knn_oracle_bruteforce(const float *q, int64_t n, const float *r, int64_t m,
+                          int32_t d, int32_t k, int32_t exclude_self,
+                          int64_t *idx_out, double *d2_out)
+{
+    if (!q || !r || !idx_out || !d2_out || n < 0 || m <= 0 || d <= 0 || k <= 0)
+        return -1;
+    if (k >= m) return -1;                     /* 0 < k < m */
+    if (exclude_self && n != m) return -1;     /* identical sets only */
+
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (i = 0; i < n; ++i) {
+        /* the list of the k best so far, ascending; slots beyond `len` are
+         * treated as +infinity (empty-list initialisation of the k-NN rule) */
+        double *bd = d2_out + i * (int64_t)k;
+        int64_t *bi = idx_out + i * (int64_t)k;
+        int len = 0;
+        const float *qi = q + i * (int64_t)d;
+        for (int64_t j = 0; j < m; ++j) {
+            if (exclude_self && j == i) continue;
+            const float *rj = r + j * (int64_t)d;
+            double s = 0.0;
+            for (int t = 0; t < d; ++t) {
+                double diff = (double)qi[t] - (double)rj[t];
+                s += diff * diff;
+            }
+            if (len == k && !before(s, j, bd[k - 1], bi[k - 1])) continue;
+            /* ordered insert, truncating the list to length k */
+            int pos = (len < k) ? len : k - 1;
+            while (pos > 0 && before(s, j, bd[pos - 1], bi[pos - 1])) {
+                bd[pos] = bd[pos - 1];
+                bi[pos] = bi[pos - 1];
+                --pos;
+            }
+            bd[pos] = s;
+            bi[pos] = j;
+            if (len < k) ++len;
+        }
+    }
+    return 0;
+}
+
+/*
+ * Same definition, for a subset of the queries: rows listed in qsel (so a
+ * benchmark can time the oracle on a bounded sample).  Row t of the outputs
+ * belongs to query qsel[t].  exclude_self compares qsel[t] with j.
+ */
+int knn_oracle_bruteforce_rows(const float *q, const int64_t *qsel, int64_t nsel,
+                               const float *r, int64_t m, int32_t d, int32_t k,
+                               int32_t exclude_self, int64_t *idx_out,
+                               double *d2_out)
+{
+    if (!q || !qsel || !r || !idx_out || !d2_out || nsel < 0 || m <= 0 || d <= 0 ||
+        k <= 0 || k >= m)
+        return -1;
+    int64_t t;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (t = 0; t < nsel; ++t) {
+        int64_t i = qsel[t];
+        double *bd = d2_out + t * (int64_t)k;
+        int64_t *bi = idx_out + t * (int64_t)k;
+        int len = 0;
+        const float *qi = q + i * (int64_t)d;
+        for (int64_t j = 0; j < m; ++j) {
+            if (exclude_self && j == i) continue;
+            const float *rj = r + j * (int64_t)d;
+            double s = 0.0;
+            for (int u = 0; u < d; ++u) {
+                double diff = (double)qi[u] - (double)rj[u];
+                s += diff * diff;
+            }
+            if (len == k && !before(s, j, bd[k - 1], bi[k - 1])) continue;
+            int pos = (len < k) ? len : k - 1;
+            while (pos > 0 && before(s, j, bd[pos - 1], bi[pos - 1])) {
+                bd[pos] = bd[pos - 1];
+                bi[pos] = bi[pos - 1];
+                --pos;
+            }
+            bd[pos] = s;
+            bi[pos] = j;
+            if (len < k) ++len;
+        }
+    }
+    return 0;
+}
+
+/*
+ * Squared distances in FP64 for explicit (query row, reference row) pairs.
+ * The parity predicate uses it to price any index the GPU returns.
+ */
+int knn_oracle_pair_d2(const float *q, const float *r, int32_t d,
+                       const int64_t *qi, const int64_t *ri, int64_t npairs,
+                       double *d2_out)
+{
+    if (!q || !r || !qi || !ri || !d2_out || d <= 0 || npairs < 0) return -1;
+    int64_t t;
+#pragma omp parallel for schedule(static)
+    for (t = 0; t < npairs; ++t) {
+        const float *a = q + qi[t] * (int64_t)d;
+        const float *b = r + ri[t] * (int64_t)d;
+        double s = 0.0;
+        for (int u = 0; u < d; ++u) {
+            double diff = (double)a[u] - (double)b[u];
+            s += diff * diff;
+        }
+        d2_out[t] = s;
+    }
+    return 0;
+}
