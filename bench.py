@@ -1,0 +1,168 @@
+"""Benchmark: exact all-kNN queries/s on one MI355X.
+
+One step = the whole job on inputs already resident in HBM: build the
+reference kd-tree, build the query kd-tree, run the pruning dual-tree search,
+write the (index, distance) lists.  W untimed warm-up steps, then K timed
+steps between device synchronisations.  Prints ONE JSON line.
+
+Default workload: 1,000,000 reference x 1,000,000 query points, d = 3,
+32-component Gaussian mixture, k = 10, leaf size 32, FP32 path.
+
+The dominant kernel is the traversal kernel; its average duration comes
+from HIP events the library records around that launch on the same stream
+(knn_stats.ms_main_kernel).  Algorithmic FLOPs per evaluated pair are
+3d - 1 (direct difference: d subtractions, d squares, d - 1 additions).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAKS = {  # MI355X published dense peaks
+    "fp32_vector_tflops": 157.3,
+    "fp64_vector_tflops": 78.6,
+    "bf16_mfma_tflops": 2500.0,
+    "hbm_gbs": 8000.0,
+}
+
+# HBM traffic of the traversal kernel measured with rocprofv3 --pmc
+# (FETCH_SIZE, WRITE_SIZE); None until measured for the current kernel.
+TRAFFIC_BYTES_PER_LAUNCH = {}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="gmm1m_d3_k10")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--bound", default="B", choices=["B", "B1", "none"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target wall time of the CPU oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(ref, q, k, self_mode, target_s):
+    """The oracle (FP64 brute force, OpenMP, all host cores) timed on a
+    seeded sample of the same queries; scaled to queries/s."""
+    import numpy as np
+
+    from oracle import knn as ok
+    qq = ref if self_mode else q
+    rng = np.random.default_rng(1234)
+    n = 64
+    elapsed = 0.0
+    while True:
+        rows = np.sort(rng.choice(len(qq), size=min(n, len(qq)), replace=False))
+        t0 = time.perf_counter()
+        ok.knn_rows(qq, rows, ref, k, exclude_self=self_mode)
+        elapsed = time.perf_counter() - t0
+        if elapsed >= target_s / 4 or n >= len(qq):
+            break
+        n = int(min(len(qq), n * max(2.0, target_s / max(elapsed, 1e-3) * 0.9)))
+    return {"value": len(rows) / elapsed, "unit": "queries/s", "cores": ok.threads(),
+            "kind": "oracle",
+            "sample": f"{len(rows)} seeded queries x all {len(ref)} references "
+                      f"(FP64 brute force), {elapsed:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; "
+                                   "--gpus must be 1 (no multi-GPU path)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1304_4327_amd import datagen, knn
+
+    ref, q, k, leaf = datagen.make(args.workload)
+    self_mode = q is None
+    d = ref.shape[1]
+    R = torch.from_numpy(ref).cuda()
+    Q = None if self_mode else torch.from_numpy(q).cuda()
+    nq = len(ref) if self_mode else len(q)
+    idx = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+    dist = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        rt = knn.knn_build_tree(R, leaf, stream=stream)
+        if self_mode:
+            _, _, st = knn.knn_search(rt, None, k, bound=args.bound, precision=args.precision,
+                                      exclude_self=True, stats=True, out=(idx, dist),
+                                      stream=stream)
+            st["ms_ref_build"] = rt.info()["ms_build"]
+        else:
+            qt = knn.knn_build_tree(Q, leaf, stream=stream)
+            _, _, st = knn.knn_search(rt, qt, k, bound=args.bound, precision=args.precision,
+                                      stats=True, out=(idx, dist), stream=stream)
+            st["ms_ref_build"] = rt.info()["ms_build"]
+            st["ms_query_build"] = qt.info()["ms_build"]
+            qt.close()
+        rt.close()
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(step())
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ms_step = total / args.steps * 1e3
+    value = nq * args.steps / total
+
+    kern_ms = float(np.mean([s["ms_main_kernel"] for s in stats]))
+    pairs = float(np.mean([s["pairs"] for s in stats]))
+    flop_per_pair = 3 * d - 1
+    achieved = pairs * flop_per_pair / (kern_ms * 1e-3) / 1e12
+    peak = PEAKS["fp32_vector_tflops"]
+    traffic = TRAFFIC_BYTES_PER_LAUNCH.get((args.workload, args.precision))
+    line = {
+        "metric": "exact kNN queries/s, 1M\u00d71M d=3 k=10; learned+BF16 vs plain FP32 speedup",
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded, generated on the host; no dataset)",
+        "config": {"workload": args.workload, "n_ref": len(ref), "n_query": nq, "d": d, "k": k,
+                   "leaf_size": leaf, "bound": args.bound, "precision": args.precision,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "k_search_valu", "kernel_ms": kern_ms,
+                     "flop_per_pair": flop_per_pair, "pairs_per_launch": pairs},
+        "breakdown_ms": {
+            "ref_build": float(np.mean([s["ms_ref_build"] for s in stats])),
+            "query_build": float(np.mean([s.get("ms_query_build", 0.0) for s in stats])),
+            "search": float(np.mean([s["ms_search"] for s in stats])),
+        },
+        "pairs_per_query": pairs / nq,
+        "score_calls": float(np.mean([s["score_calls"] for s in stats])),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(ref, q, k, self_mode, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

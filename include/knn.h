@@ -1,0 +1,183 @@
+/*
+ * knn.h -- exact k-nearest-neighbour search by a pruning dual-tree traversal
+ * over kd-trees, on AMD MI355X (gfx950).  C ABI.
+ *
+ * The method is the dual-tree meta-algorithm of Curtin et al.,
+ * "Tree-Independent Dual-Tree Algorithms" (ICML 2013): a space tree (here a
+ * kd-tree, Section "Space Trees"), a pruning dual-tree traversal (Section
+ * "Tree Traversals", Algorithm 1), the k-NN BaseCase (Algorithm 2) and the
+ * k-NN Score with the node bound B(N_q) (Algorithm 3 and the bound
+ * equations of Section "k-Nearest Neighbor Search").
+ *
+ * Conventions for every entry point
+ *   - Point arrays are row-major FP32, n rows of d values, in DEVICE memory
+ *     unless the argument says "host".  The caller owns every buffer it
+ *     passes; the library never frees or retains caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; every call synchronises that stream before it
+ *     returns, so the status reflects device-side errors.
+ *   - Nothing is thrown across the ABI.  Arguments are validated before any
+ *     device work; on error the outputs are unspecified and
+ *     knn_last_error() describes the failure (thread-local string).
+ *   - Opaque handles (knn_tree, knn_mlp) own device memory on the device that
+ *     was current when they were created; free them with the matching
+ *     *_free call.
+ */
+#ifndef KNN_DUALTREE_H
+#define KNN_DUALTREE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum knn_status {
+    KNN_OK = 0,
+    KNN_E_INVALID_ARG = 1, /* argument outside the documented domain        */
+    KNN_E_NONFINITE = 2,   /* NaN or Inf in an input coordinate             */
+    KNN_E_OOM = 3,         /* device allocation failed                      */
+    KNN_E_DEVICE = 4,      /* HIP runtime error (no device, launch failure) */
+    KNN_E_MODEL = 5,       /* seed-network file unreadable or inconsistent  */
+    KNN_E_UNSUPPORTED = 6  /* valid request this build does not implement   */
+} knn_status;
+
+/* Pruning bound used by Score() (Section "k-Nearest Neighbor Search").
+ * KNN_BOUND_B    combined bound B(N_q) = min{ B1(N_q),
+ *                min_{p in D^p_q} D_p[k] + rho + lambda, B(Par(N_q)) }; at a
+ *                kd-tree leaf rho = lambda, so the middle term is
+ *                min D_p[k] + 2 lambda(N_q).  The printed child term
+ *                B(N_c) + 2(lambda_q - lambda_c) is not used: it is not an
+ *                upper bound when B(N_c) is attained by its max term.
+ * KNN_BOUND_B1   B1(N_q) = max_{p in D^p_q} D_p[k] (Gray's AllNN rule,
+ *                Algorithm 4, generalised to k).
+ * KNN_BOUND_NONE no pruning: every (query leaf, reference leaf) pair is
+ *                evaluated (the non-pruning traversal of the correctness
+ *                argument; brute force through the same kernels).
+ * Every mode prunes only when d_min exceeds the bound strictly (with a
+ * relative slack of 2^-16 for FP32 rounding), never at equality. */
+typedef enum knn_bound { KNN_BOUND_B = 0, KNN_BOUND_B1 = 1, KNN_BOUND_NONE = 2 } knn_bound;
+
+/* Arithmetic of BaseCase() distance evaluation.
+ * KNN_PREC_FP32  FP32 direct difference ||p_q - p_r||^2 on the vector ALUs;
+ *                for d > 8 every candidate that passes the FP32 filter is
+ *                re-scored in FP64 before it enters a k-list.
+ * KNN_PREC_BF16  BF16 matrix-core (MFMA) tiles, FP32 accumulation, of the
+ *                centred Gram form ||q||^2 + ||r||^2 - 2 q.r; a candidate is
+ *                kept when the BF16 value minus a proven error margin beats
+ *                the current k-th distance, and is then re-scored in FP64.
+ * Both modes return the same exact answer (see knn_search). */
+typedef enum knn_precision { KNN_PREC_FP32 = 0, KNN_PREC_BF16 = 1 } knn_precision;
+
+/* Counters of one knn_search call (filled when knn_opts.stats != NULL). */
+typedef struct knn_stats {
+    int64_t score_calls;      /* Score() evaluations (reference nodes tested)   */
+    int64_t leaf_tiles;       /* (query-leaf group, reference leaf) tiles       */
+    int64_t pairs;            /* BaseCase() point pairs evaluated                */
+    int64_t inserts;          /* candidates inserted into a k-list               */
+    int64_t fallback_leaves;  /* query leaves searched again without their seed  */
+    int64_t fallback_queries; /* queries whose k-th distance exceeded the seed   */
+    float ms_query_build;     /* device time, query-tree build (0 if reused)     */
+    float ms_search;          /* device time, traversal incl. fallback           */
+    float ms_main_kernel;     /* device time of the main traversal launch        */
+    int32_t n_query_leaves;   /* leaves of the query tree                        */
+} knn_stats;
+
+typedef struct knn_opts {
+    int32_t bound;              /* knn_bound                                       */
+    int32_t precision;          /* knn_precision                                   */
+    int32_t exclude_self;       /* 1: skip reference i for query i (footnote to
+                                   Algorithm 2); only with query tree == ref tree  */
+    int32_t reserved;           /* must be 0                                       */
+    const float *seed_radius;   /* device, one per query leaf (distance units), or
+                                   NULL.  Initial bound of that leaf; a leaf with a
+                                   query whose k-th distance exceeds it is searched
+                                   again without it, so any values keep the answer
+                                   exact.                                          */
+    float *leaf_kth_out;        /* device, one per query leaf, or NULL: largest
+                                   final k-th distance in the leaf (the final
+                                   B1 of the leaf)                                 */
+    knn_stats *stats;           /* host, or NULL                                   */
+} knn_opts;
+
+/* Fill *opts with the defaults: bound B, FP32, no self exclusion, no seed. */
+void knn_opts_default(knn_opts *opts);
+
+const char *knn_status_string(knn_status s);
+/* Description of the last error on the calling thread ("" if none). */
+const char *knn_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * kd-tree (Section "Space Trees", Definition 1; kd-tree bounds paragraph).
+ * ------------------------------------------------------------------------ */
+typedef struct knn_tree knn_tree;
+
+/* Build a kd-tree over `points` (device, n x d FP32 row-major).
+ * Split rule: complete tree of depth L = smallest L with
+ * ceil(n / 2^L) <= leaf_size, heap-ordered nodes; a node splits on the
+ * dimension of largest FP32 box extent (ties: lowest), the left child takes
+ * the floor(n/2) smallest points by (coordinate, original index), both
+ * children keep ascending original-index order; points live only in leaves.
+ * Node data: tight FP32 box, centre fl(0.5 fl(lo+hi)), lambda = max distance
+ * from the centre to a descendant point (leaves: exact, rounded up to FP32;
+ * internal nodes: an upper bound from the children).
+ * The tree copies the points (permuted); the caller may free `points` after
+ * the call.  Domain: n >= 1 (n < 2^31), 1 <= d <= 64, 1 <= leaf_size <= 64.
+ * Errors: KNN_E_INVALID_ARG, KNN_E_NONFINITE, KNN_E_OOM, KNN_E_DEVICE. */
+knn_status knn_build_tree(const float *points, int64_t n, int32_t d, int32_t leaf_size,
+                          void *stream, knn_tree **out);
+void knn_free_tree(knn_tree *tree);
+
+/* Read-only view of a tree's device arrays (for tests and tools).
+ * Layout: dp = d rounded up to 4, 8, 16, 32 or 64 (padding coordinates are 0).
+ *   points     (n + 64) x dp FP32, tree order (last 64 rows zero padding)
+ *   perm       n int32: original row of tree position i
+ *   node_range n_nodes x 2 int32: start, count (heap order)
+ *   box        n_nodes x 2 x dp FP32: lo[dp] then hi[dp]
+ *   lambda     n_nodes FP32
+ *   split_dim  n_nodes int32 (-1 at leaves) */
+typedef struct knn_tree_info {
+    int64_t n;
+    int32_t d, dp, leaf_size, depth;
+    int64_t n_nodes, n_leaves, first_leaf;
+    const float *points;
+    const int32_t *perm;
+    const int32_t *node_range;
+    const float *box;
+    const float *lambda;
+    const int32_t *split_dim;
+    float ms_build; /* device time of the build */
+} knn_tree_info;
+knn_status knn_tree_get_info(const knn_tree *tree, knn_tree_info *info);
+
+/* ------------------------------------------------------------------------
+ * Search (Section "k-Nearest Neighbor Search": for each query point the k
+ * nearest reference points and their distances, 0 < k < m).
+ * ------------------------------------------------------------------------ */
+
+/* All k nearest neighbours of every point of `query` among the points of
+ * `ref`.  query == NULL or query == ref: all-kNN of ref on itself (set
+ * opts->exclude_self to skip each point's own index).
+ * Outputs (device, caller-owned, n_q x k row-major, rows in original query
+ * order): idx_out = original reference row, dist_out = Euclidean distance
+ * (FP32, from an FP64 evaluation), ascending; equal distances are ordered by
+ * reference index.  The answer is exact: the index set equals the FP64
+ * brute-force set except where FP64 distances tie within 1e-6 relative at
+ * the k-th place.  Domain: 1 <= k <= 64 and k < m; with exclude_self the
+ * m - 1 other points are the candidates (the same condition) and k <= 63.
+ * Same d in both trees.  opts == NULL means the defaults. */
+knn_status knn_search(const knn_tree *ref, const knn_tree *query, int32_t k,
+                      const knn_opts *opts, int64_t *idx_out, float *dist_out,
+                      void *stream);
+
+/* Convenience: builds the query tree from `queries` (device, n_q x d) with
+ * the reference tree's leaf size, searches, frees it.  The query-tree build
+ * time is reported in stats->ms_query_build. */
+knn_status knn_search_points(const knn_tree *ref, const float *queries, int64_t n_q,
+                             int32_t k, const knn_opts *opts, int64_t *idx_out,
+                             float *dist_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KNN_DUALTREE_H */

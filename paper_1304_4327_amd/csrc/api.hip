@@ -1,0 +1,300 @@
+// C-ABI entry points (include/knn.h): argument validation, allocation of
+// per-call scratch on the caller's stream, kernel dispatch, status codes.
+#include "search.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+namespace knnx {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+const char *get_error() { return g_last_error.c_str(); }
+
+knn_status fail(knn_status code, const std::string &msg) {
+    set_error(msg);
+    return code;
+}
+
+knn_status hip_fail(hipError_t e, const char *what, const char *file, int line) {
+    std::string m = std::string(what) + " failed: " + hipGetErrorString(e) + " (" + file + ":" +
+                    std::to_string(line) + ")";
+    set_error(m);
+    return e == hipErrorOutOfMemory ? KNN_E_OOM : KNN_E_DEVICE;
+}
+
+namespace {
+
+hipError_t launch_valu(const SearchArgs &a, int d, int K, int grid, hipStream_t s) {
+    switch (d <= 4 ? d : pad_dim(d)) {
+        case 1: return launch_search_valu_d1(a, K, grid, s);
+        case 2: return launch_search_valu_d2(a, K, grid, s);
+        case 3: return launch_search_valu_d3(a, K, grid, s);
+        case 4: return launch_search_valu_d4(a, K, grid, s);
+        case 8: return launch_search_valu_d8(a, K, grid, s);
+        case 16: return launch_search_valu_d16(a, K, grid, s);
+        case 32: return launch_search_valu_d32(a, K, grid, s);
+        default: return launch_search_valu_d64(a, K, grid, s);
+    }
+}
+
+__global__ void k_compact_fallback(const int *__restrict__ flag, int n, int *__restrict__ list,
+                                   int *__restrict__ count) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flag[i]) list[atomicAdd(count, 1)] = i;
+}
+
+struct Scratch {
+    hipStream_t s;
+    std::vector<void *> p;
+    template <class T>
+    hipError_t get(T **out, size_t n) {
+        hipError_t e = alloc_async(out, n, s);
+        if (e == hipSuccess) p.push_back(*out);
+        return e;
+    }
+    ~Scratch() {
+        for (void *q : p) free_async(q, s);
+    }
+};
+
+knn_status validate_tree(const knn_tree *t, const char *who) {
+    if (!t) return fail(KNN_E_INVALID_ARG, std::string(who) + ": tree is NULL");
+    return KNN_OK;
+}
+
+}  // namespace
+
+knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_opts *opts_in,
+                  int64_t *idx_out, float *dist_out, hipStream_t s) {
+    KNN_TRY(validate_tree(ref, "knn_search"));
+    knn_opts opts;
+    knn_opts_default(&opts);
+    if (opts_in) opts = *opts_in;
+    const knn_tree *qt = query ? query : ref;
+    const bool same = qt == ref;
+    if (!idx_out || !dist_out) return fail(KNN_E_INVALID_ARG, "knn_search: output pointer is NULL");
+    if (qt->d != ref->d) return fail(KNN_E_INVALID_ARG, "knn_search: query and reference d differ");
+    if (k < 1 || k > 64) return fail(KNN_E_INVALID_ARG, "knn_search: need 1 <= k <= 64");
+    if (int64_t(k) >= ref->n)
+        return fail(KNN_E_INVALID_ARG, "knn_search: need k < m (number of reference points)");
+    if (opts.exclude_self && !same)
+        return fail(KNN_E_INVALID_ARG,
+                    "knn_search: exclude_self needs the query tree to be the reference tree");
+    if (opts.bound < 0 || opts.bound > 2) return fail(KNN_E_INVALID_ARG, "knn_search: bad bound");
+    if (opts.precision < 0 || opts.precision > 1)
+        return fail(KNN_E_INVALID_ARG, "knn_search: bad precision");
+    if (opts.reserved != 0) return fail(KNN_E_INVALID_ARG, "knn_search: reserved field must be 0");
+    if (opts.precision == KNN_PREC_BF16)
+        return fail(KNN_E_UNSUPPORTED, "knn_search: BF16 tiles are not built into this library");
+
+    if (opts.exclude_self && k > 63)
+        return fail(KNN_E_INVALID_ARG, "knn_search: need k <= 63 with exclude_self");
+    const int K = list_size_for(k + (opts.exclude_self ? 1 : 0));
+    int max_leaf = int((qt->n + qt->n_leaves - 1) / qt->n_leaves);
+    int lpl_log2 = 0;
+    while ((1 << lpl_log2) < max_leaf) ++lpl_log2;
+    if (qt->dp >= 32) lpl_log2 = 6;
+    const int NG = 64 >> lpl_log2;
+    const int nq_leaves = int(qt->n_leaves);
+
+    Scratch sc{s, {}};
+    unsigned long long *dstats = nullptr;
+    if (opts.stats) {
+        KNN_HIP(sc.get(&dstats, ST_COUNT));
+        KNN_HIP(hipMemsetAsync(dstats, 0, ST_COUNT * sizeof(unsigned long long), s));
+    }
+    int *fb_flag = nullptr, *fb_list = nullptr, *fb_count = nullptr;
+    if (opts.seed_radius) {
+        KNN_HIP(sc.get(&fb_flag, nq_leaves));
+        KNN_HIP(sc.get(&fb_list, nq_leaves));
+        KNN_HIP(sc.get(&fb_count, 1));
+        KNN_HIP(hipMemsetAsync(fb_flag, 0, nq_leaves * sizeof(int), s));
+        KNN_HIP(hipMemsetAsync(fb_count, 0, sizeof(int), s));
+    }
+
+    SearchArgs a{};
+    a.rpts = ref->pts;
+    a.rperm = ref->perm;
+    a.rrange = ref->range;
+    a.rbox = ref->box;
+    a.rlpts = ref->lpts;
+    a.r_leaf_slots = ref->leaf_slots;
+    a.r_first_leaf = int(ref->first_leaf);
+    a.qpts = qt->pts;
+    a.qperm = qt->perm;
+    a.qrange = qt->range;
+    a.qbox = qt->box;
+    a.qlam = qt->lam;
+    a.q_first_leaf = int(qt->first_leaf);
+    a.q_n_leaves = nq_leaves;
+    a.leaf_list = nullptr;
+    a.n_list_dev = nullptr;
+    a.d = ref->d;
+    a.k = k;
+    a.lpl_log2 = lpl_log2;
+    a.bound = opts.bound;
+    a.self = opts.exclude_self ? 1 : 0;
+    a.seed = opts.seed_radius;
+    a.out_idx = idx_out;
+    a.out_dist = dist_out;
+    a.leaf_kth = opts.leaf_kth_out;
+    a.fallback = fb_flag;
+    a.stats = dstats;
+    // debug aid: KNN_WAVE_LOG=<file> writes per-wave counters of the main launch
+    const char *wlog_path = std::getenv("KNN_WAVE_LOG");
+    uint32_t *wlog = nullptr;
+
+    const int waves = (nq_leaves + NG - 1) / NG;
+    const int grid = (waves + 3) / 4;
+    if (wlog_path) {
+        KNN_HIP(sc.get(&wlog, size_t(grid) * 4 * 8));
+        KNN_HIP(hipMemsetAsync(wlog, 0, size_t(grid) * 32 * sizeof(uint32_t), s));
+        a.wave_log = wlog;
+    }
+    hipEvent_t ev[4];
+    for (auto &e : ev) KNN_HIP(hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+        }
+    } eg{ev};
+    KNN_HIP(hipEventRecord(ev[0], s));
+    KNN_HIP(launch_valu(a, ref->d, K, grid, s));
+    KNN_HIP(hipEventRecord(ev[1], s));
+    if (opts.seed_radius) {
+        k_compact_fallback<<<(nq_leaves + 255) / 256, 256, 0, s>>>(fb_flag, nq_leaves, fb_list,
+                                                                   fb_count);
+        SearchArgs b = a;
+        b.seed = nullptr;
+        b.fallback = nullptr;
+        b.leaf_list = fb_list;
+        b.n_list_dev = fb_count;
+        b.wave_log = nullptr;
+        KNN_HIP(launch_valu(b, ref->d, K, grid, s));
+    }
+    KNN_HIP(hipEventRecord(ev[2], s));
+    unsigned long long hst[ST_COUNT] = {};
+    int hfb = 0;
+    if (dstats)
+        KNN_HIP(hipMemcpyAsync(hst, dstats, sizeof(hst), hipMemcpyDeviceToHost, s));
+    if (fb_count) KNN_HIP(hipMemcpyAsync(&hfb, fb_count, sizeof(int), hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipStreamSynchronize(s));
+    if (wlog) {
+        std::vector<uint32_t> h(size_t(grid) * 32);
+        KNN_HIP(hipMemcpy(h.data(), wlog, h.size() * 4, hipMemcpyDeviceToHost));
+        if (FILE *f = std::fopen(wlog_path, "wb")) {
+            std::fwrite(h.data(), 4, h.size(), f);
+            std::fclose(f);
+        }
+    }
+    if (opts.stats) {
+        knn_stats *st = opts.stats;
+        st->score_calls = int64_t(hst[ST_SCORE]);
+        st->leaf_tiles = int64_t(hst[ST_TILES]);
+        st->pairs = int64_t(hst[ST_PAIRS]);
+        st->inserts = int64_t(hst[ST_INSERTS]);
+        st->fallback_queries = int64_t(hst[ST_FB_QUERIES]);
+        st->fallback_leaves = hfb;
+        (void)hipEventElapsedTime(&st->ms_main_kernel, ev[0], ev[1]);
+        (void)hipEventElapsedTime(&st->ms_search, ev[0], ev[2]);
+        st->n_query_leaves = nq_leaves;
+    }
+    return KNN_OK;
+}
+
+}  // namespace knnx
+
+using namespace knnx;
+
+extern "C" {
+
+void knn_opts_default(knn_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->bound = KNN_BOUND_B;
+    o->precision = KNN_PREC_FP32;
+}
+
+const char *knn_status_string(knn_status s) {
+    switch (s) {
+        case KNN_OK: return "ok";
+        case KNN_E_INVALID_ARG: return "invalid argument";
+        case KNN_E_NONFINITE: return "non-finite input";
+        case KNN_E_OOM: return "out of device memory";
+        case KNN_E_DEVICE: return "device error";
+        case KNN_E_MODEL: return "seed model error";
+        case KNN_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *knn_last_error(void) { return get_error(); }
+
+knn_status knn_build_tree(const float *points, int64_t n, int32_t d, int32_t leaf_size,
+                          void *stream, knn_tree **out) {
+    set_error("");
+    if (!out) return fail(KNN_E_INVALID_ARG, "knn_build_tree: out is NULL");
+    *out = nullptr;
+    if (!points) return fail(KNN_E_INVALID_ARG, "knn_build_tree: points is NULL");
+    if (n < 1 || n >= (int64_t(1) << 31) - 64)
+        return fail(KNN_E_INVALID_ARG, "knn_build_tree: need 1 <= n < 2^31 - 64");
+    if (d < 1 || d > 64) return fail(KNN_E_INVALID_ARG, "knn_build_tree: need 1 <= d <= 64");
+    if (leaf_size < 1 || leaf_size > 64)
+        return fail(KNN_E_INVALID_ARG, "knn_build_tree: need 1 <= leaf_size <= 64");
+    return build_tree(points, n, d, leaf_size, (hipStream_t)stream, out);
+}
+
+void knn_free_tree(knn_tree *tree) { free_tree(tree); }
+
+knn_status knn_tree_get_info(const knn_tree *t, knn_tree_info *info) {
+    if (!t || !info) return fail(KNN_E_INVALID_ARG, "knn_tree_get_info: NULL argument");
+    info->n = t->n;
+    info->d = t->d;
+    info->dp = t->dp;
+    info->leaf_size = t->leaf_size;
+    info->depth = t->depth;
+    info->n_nodes = t->n_nodes;
+    info->n_leaves = t->n_leaves;
+    info->first_leaf = t->first_leaf;
+    info->points = t->pts;
+    info->perm = t->perm;
+    info->node_range = reinterpret_cast<const int32_t *>(t->range);
+    info->box = t->box;
+    info->lambda = t->lam;
+    info->split_dim = t->split_dim;
+    info->ms_build = t->ms_build;
+    return KNN_OK;
+}
+
+knn_status knn_search(const knn_tree *ref, const knn_tree *query, int32_t k,
+                      const knn_opts *opts, int64_t *idx_out, float *dist_out, void *stream) {
+    set_error("");
+    return search(ref, query, k, opts, idx_out, dist_out, (hipStream_t)stream);
+}
+
+knn_status knn_search_points(const knn_tree *ref, const float *queries, int64_t n_q, int32_t k,
+                             const knn_opts *opts, int64_t *idx_out, float *dist_out,
+                             void *stream) {
+    set_error("");
+    KNN_TRY(validate_tree(ref, "knn_search_points"));
+    if (!queries) return fail(KNN_E_INVALID_ARG, "knn_search_points: queries is NULL");
+    if (opts && opts->exclude_self)
+        return fail(KNN_E_INVALID_ARG,
+                    "knn_search_points: exclude_self needs the query tree to be the reference tree");
+    knn_tree *qt = nullptr;
+    knn_status st = knn_build_tree(queries, n_q, ref->d, ref->leaf_size, stream, &qt);
+    if (st != KNN_OK) return st;
+    st = search(ref, qt, k, opts, idx_out, dist_out, (hipStream_t)stream);
+    if (st == KNN_OK && opts && opts->stats) opts->stats->ms_query_build = qt->ms_build;
+    free_tree(qt);
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Internal definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "knn.h"
+
+// ---------------------------------------------------------------------------
+// error plumbing: every C-ABI entry point returns a knn_status and records a
+// message in a thread-local string.
+// ---------------------------------------------------------------------------
+namespace knnx {
+
+void set_error(const std::string &msg);
+const char *get_error();
+
+struct Status {
+    knn_status code = KNN_OK;
+    bool ok() const { return code == KNN_OK; }
+};
+
+knn_status fail(knn_status code, const std::string &msg);
+knn_status hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+}  // namespace knnx
+
+#define KNN_HIP(expr)                                                          \
+    do {                                                                       \
+        hipError_t _e = (expr);                                                \
+        if (_e != hipSuccess) return knnx::hip_fail(_e, #expr, __FILE__, __LINE__); \
+    } while (0)
+
+#define KNN_TRY(expr)                                                          \
+    do {                                                                       \
+        knn_status _s = (expr);                                                \
+        if (_s != KNN_OK) return _s;                                           \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// kd-tree handle.  Nodes are in heap order: children of i are 2i+1, 2i+2;
+// node i at depth l covers a contiguous range of the tree-ordered points.
+// ---------------------------------------------------------------------------
+struct knn_tree {
+    int64_t n = 0;
+    int32_t d = 0, dp = 0, leaf_size = 0, depth = 0;
+    int64_t n_nodes = 0, n_leaves = 0, first_leaf = 0;
+    float *pts = nullptr;         // (n + kPadRows) x dp, tree order, zero padded
+    float *lpts = nullptr;        // n_leaves x leaf_slots x dp: each leaf's points in a
+                                  // fixed block, unused slots FLT_MAX (never a candidate)
+    int32_t leaf_slots = 0;       // largest leaf, rounded up to a multiple of 8
+    int32_t *perm = nullptr;      // n: original row of tree position
+    int2 *range = nullptr;        // n_nodes: (start, count)
+    float *box = nullptr;         // n_nodes x 2 x dp: lo, hi
+    float *lam = nullptr;         // n_nodes
+    int32_t *split_dim = nullptr; // n_nodes
+    int device = 0;
+    float ms_build = 0.f;
+};
+
+namespace knnx {
+
+constexpr int kPadRows = 64;  // zero rows after the last point: tile loops may
+                              // read a whole 64-row window past any leaf start
+
+inline int pad_dim(int d) {
+    if (d <= 4) return 4;
+    if (d <= 8) return 8;
+    if (d <= 16) return 16;
+    if (d <= 32) return 32;
+    return 64;
+}
+
+inline int depth_for(int64_t n, int leaf) {
+    int L = 0;
+    while (((n + (int64_t(1) << L) - 1) >> L) > leaf) ++L;
+    return L;
+}
+
+// FP32 -> order-preserving uint32 (after mapping -0 to +0, so that equal
+// floats give equal keys).
+__host__ __device__ inline uint32_t f2key(float f) {
+    if (f == 0.0f) f = 0.0f;
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float key2f(uint32_t k) {
+    uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+
+// tree construction (tree_build.hip)
+knn_status build_tree(const float *points, int64_t n, int d, int leaf, hipStream_t s,
+                      knn_tree **out);
+void free_tree(knn_tree *t);
+
+// stream-ordered scratch allocation
+template <class T>
+inline hipError_t alloc_async(T **p, size_t count, hipStream_t s) {
+    return hipMallocAsync(reinterpret_cast<void **>(p), count * sizeof(T) + 256, s);
+}
+inline void free_async(void *p, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+}  // namespace knnx

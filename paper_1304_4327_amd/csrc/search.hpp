@@ -1,0 +1,72 @@
+// Search-side declarations shared by the traversal kernels and the host code.
+#pragma once
+
+#include "common.hpp"
+
+namespace knnx {
+
+// counters accumulated by the traversal kernels (uint64 each)
+enum StatSlot {
+    ST_SCORE = 0,
+    ST_TILES = 1,
+    ST_PAIRS = 2,
+    ST_INSERTS = 3,
+    ST_FB_QUERIES = 4,
+    ST_COUNT = 8
+};
+
+struct SearchArgs {
+    // reference tree
+    const float *rpts;
+    const int32_t *rperm;
+    const int2 *rrange;
+    const float *rbox;
+    const float *rlpts;  // leaf-blocked points (r_leaf_slots per leaf)
+    int r_leaf_slots;
+    int r_first_leaf;
+    // query tree
+    const float *qpts;
+    const int32_t *qperm;
+    const int2 *qrange;
+    const float *qbox;
+    const float *qlam;
+    int q_first_leaf;
+    int q_n_leaves;
+    // work list: query leaves to process.  leaf_list == NULL means all
+    // leaves 0..q_n_leaves-1; otherwise *n_list_dev entries.
+    const int *leaf_list;
+    const int *n_list_dev;
+    int d, k, lpl_log2;
+    int bound;          // knn_bound
+    int self;           // exclude reference position == query position
+    const float *seed;  // per query leaf, or NULL
+    int64_t *out_idx;
+    float *out_dist;
+    float *leaf_kth;    // per query leaf, or NULL
+    int *fallback;      // per query leaf flag (seeded runs), or NULL
+    unsigned long long *stats;  // ST_COUNT counters, or NULL
+    uint32_t *wave_log;         // debug: 8 words per wave (ticks, scores, tiles, inserts, passes, leaf)
+};
+
+// per-dimension launchers (search_d*.hip): D computed dimensions (d for
+// d <= 4, else d rounded up to 8, 16, 32 or 64 with zero padding); K is
+// the compile-time list length
+hipError_t launch_search_valu_d1(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_valu_d2(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_valu_d3(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_valu_d4(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_valu_d8(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_valu_d16(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_valu_d32(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_valu_d64(const SearchArgs &a, int K, int grid, hipStream_t s);
+
+// compile-time list lengths; a request for a list of kk entries (k, or k+1
+// when the query's own point shares the list) uses the smallest K >= kk
+constexpr int kListSizes[] = {4, 5, 8, 10, 11, 16, 32, 50, 51, 64};
+inline int list_size_for(int kk) {
+    for (int K : kListSizes)
+        if (K >= kk) return K;
+    return -1;
+}
+
+}  // namespace knnx

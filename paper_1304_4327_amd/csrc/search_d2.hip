@@ -1,0 +1,8 @@
+// Instantiation of the FP32 traversal kernel for 2 computed dimensions.
+#include "search_valu.hpp"
+
+namespace knnx {
+hipError_t launch_search_valu_d2(const SearchArgs &a, int K, int grid, hipStream_t s) {
+    return launch_search_valu<2>(a, K, grid, s);
+}
+}  // namespace knnx

@@ -1,0 +1,8 @@
+// Instantiation of the FP32 traversal kernel for 32 computed dimensions.
+#include "search_valu.hpp"
+
+namespace knnx {
+hipError_t launch_search_valu_d32(const SearchArgs &a, int K, int grid, hipStream_t s) {
+    return launch_search_valu<32>(a, K, grid, s);
+}
+}  // namespace knnx

@@ -1,0 +1,410 @@
+// FP32 traversal kernel: the pruning dual-tree traversal (Algorithm 1) with
+// the k-NN Score (Algorithm 3) and BaseCase (Algorithm 2), one wavefront per
+// group of query leaves.
+//
+// Mapping
+//   * a wavefront owns NG = 64 / LPL consecutive query leaves (LPL = lanes per
+//     leaf, a power of two >= the largest leaf); lane = one query point;
+//   * it walks the reference tree depth first, nearer child first (the
+//     closer-of / farther-of order of Gray's AllNN, Algorithm 4), without a
+//     stack: one bit per depth records which child was entered first, and the
+//     farther child is re-scored when the walk climbs back (bounds only
+//     tighten, so the re-score can only prune more);
+//   * Score: each query point is scored as a singleton child of its leaf, so
+//     N_q = {p}, d_min(N_q, N_r) = distance from p to the node's box, and
+//     B(N_q) = min(D_p[k], B(leaf)) (B1({p}) = D_p[k], lambda = 0, and the
+//     parent term).  The wave enters a node when any of its points would;
+//   * reference nodes are wave-uniform (scalar loads); a reference leaf is the
+//     BaseCase tile, read from the leaf-blocked copy of the points (fixed
+//     slots per leaf, unused slots at FLT_MAX so their distance is +inf);
+//   * the k-list is a sorted register array of K slots; for k < K the first
+//     K-k slots hold -inf and never move, so the k-th value is always slot
+//     K-1 (the list is "ordered by ascending distance", Algorithm 2);
+//   * after each tile the leaf bound is refreshed:
+//        B1 = max over the leaf's queries of D_p[k]              (B1(N_q))
+//        B2 = min over the leaf's queries of D_p[k] + 2 lambda    (rho = lambda)
+//        BP = min over the queries of an ancestor + 2 lambda(anc) (B(Par))
+//        B  = min(B1, B2, BP, seed)
+//     and a node is pruned when d_min^2 > B^2 (1 + 2^-16).
+//   * all-kNN of a set on itself keeps k+1 entries per list; the query's own
+//     point (distance 0) takes one of them and is dropped at write-out, so no
+//     per-pair index test is needed.
+//
+// Precision.  Distances are squared FP32 direct differences over the D
+// computed dimensions.  For D > 8 a candidate passing the FP32 filter is
+// re-scored in FP64 before it enters the list (RESCORE), because the FP32
+// error (d+2) u can exceed the 1e-6 relative acceptance window at high d.
+// The final k entries are always re-scored in FP64 and sorted by
+// (distance, original index).
+#pragma once
+
+#include "search.hpp"
+
+namespace knnx {
+
+__device__ inline int xcd_remap(int b, int nblk) {
+    // hardware deals consecutive workgroups round-robin over 8 XCDs; give
+    // each XCD a contiguous run of logical blocks (spatially close query
+    // leaves share reference nodes in that XCD's L2)
+    const int q = nblk >> 3, r = nblk & 7;
+    const int x = b & 7, i = b >> 3;
+    return x * q + min(x, r) + i;
+}
+
+__device__ inline float uniform_f(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ inline int uniform_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+constexpr int stride_for(int D) { return D <= 4 ? 4 : D <= 8 ? 8 : D <= 16 ? 16 : D <= 32 ? 32 : 64; }
+
+template <int D>
+__device__ inline double d2_fp64(const float (&q)[D], const float *r) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        double t = (double)q[j] - (double)r[j];
+        s = fma(t, t, s);
+    }
+    return s;
+}
+
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
+    constexpr int DP = stride_for(D);
+    constexpr bool RESCORE = D > 8;
+    constexpr float kInf = __builtin_inff();
+    constexpr float kSlack = 1.0f + 0x1p-16f;            // prune slack (squared)
+    constexpr float kGamma = 1.0f + (D + 6) * 0x1p-24f;  // FP32 filter slack
+    const uint64_t t_start = a.wave_log ? wall_clock64() : 0;
+    const int lane = threadIdx.x & 63;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int wave = blk * 4 + (threadIdx.x >> 6);
+    const int lpl_log2 = a.lpl_log2;
+    const int NG = 64 >> lpl_log2;
+    const int n_list = a.leaf_list ? *a.n_list_dev : a.q_n_leaves;
+    if (wave * NG >= n_list) return;
+    const int g = lane >> lpl_log2, li = lane & ((1 << lpl_log2) - 1);
+    const int slot = wave * NG + g;
+    const bool has_leaf = slot < n_list;
+    const int qleaf = has_leaf ? (a.leaf_list ? a.leaf_list[slot] : slot) : 0;
+    const int qnode = a.q_first_leaf + qleaf;
+    const int2 qr = has_leaf ? a.qrange[qnode] : make_int2(0, 0);
+    const bool valid = has_leaf && li < qr.y;
+    const int qpos = qr.x + li;
+    const int kk = a.k + (a.self ? 1 : 0);  // list length (self match included)
+
+    float q[D];
+    // union box of the wave's query leaves: every lane holds the same
+    // values, so the visit-order key computed from it is wave-uniform
+    float ulo[D], uhi[D];
+    {
+        const float *qp = a.qpts + int64_t(valid ? qpos : 0) * DP;
+        const float *qb = a.qbox + int64_t(has_leaf ? qnode : 0) * 2 * DP;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            q[j] = valid ? qp[j] : 0.f;
+            float lo = has_leaf ? qb[j] : kInf;
+            float hi = has_leaf ? qb[DP + j] : -kInf;
+            for (int off = (1 << lpl_log2); off < 64; off <<= 1) {
+                lo = fminf(lo, __shfl_xor(lo, off));
+                hi = fmaxf(hi, __shfl_xor(hi, off));
+            }
+            ulo[j] = lo;
+            uhi[j] = hi;
+        }
+    }
+    const float lam2 = has_leaf ? 2.0f * a.qlam[qnode] : 0.f;
+    // a seed is only a pruning radius; NaN or negative values prune
+    // everything and send the leaf to the fallback pass
+    const float seed = (a.seed && has_leaf) ? fmaxf(a.seed[qleaf], 0.0f) : kInf;
+    const float seed2 = seed * seed;
+
+    float dist[K];
+    int idx[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        dist[j] = (j < K - kk) ? -kInf : kInf;
+        idx[j] = -1;
+    }
+    float bound2 = (a.bound == KNN_BOUND_NONE) ? kInf : seed2;
+    uint32_t n_score = 0, n_tiles = 0, n_ins = 0, n_pass = 0;
+    uint64_t n_pairs = 0;
+    const int n_valid = __popcll(ballot(valid));
+
+    // per-point bound: min(D_p[k], B(leaf)); +inf without pruning
+    auto point_bound2 = [&]() -> float {
+        return a.bound == KNN_BOUND_NONE ? kInf : fminf(bound2, dist[K - 1]);
+    };
+
+    // Score a reference node from its box: keep when any point's d_min^2 to
+    // the box is within its bound; the visit-order key is the wave-uniform
+    // d_min^2 between the union of the wave's leaf boxes and the node's box
+    auto score_box = [&](const float *b, float &key_out) -> bool {
+        float s = 0.f, u = 0.f;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const float lo = b[j], hi = b[DP + j];
+            const float gap = fmaxf(fmaxf(lo - q[j], q[j] - hi), 0.0f);
+            s = fmaf(gap, gap, s);
+            const float ug = fmaxf(fmaxf(lo - uhi[j], ulo[j] - hi), 0.0f);
+            u = fmaf(ug, ug, u);
+        }
+        const bool keep = valid && !(s > point_bound2() * kSlack);
+        key_out = uniform_f(u);
+        return ballot(keep) != 0;
+    };
+    auto score = [&](int node, float &key_out) -> bool {
+        ++n_score;
+        return score_box(a.rbox + int64_t(node) * 2 * DP, key_out);
+    };
+    // both children of an internal node: their boxes are adjacent
+    auto score_children = [&](int c0, bool &k0, bool &k1, float &m0, float &m1) {
+        n_score += 2;
+        const float *b = a.rbox + int64_t(c0) * 2 * DP;
+        k0 = score_box(b, m0);
+        k1 = score_box(b + 2 * DP, m1);
+    };
+
+    auto insert = [&](float x, int id) {
+#pragma unroll
+        for (int j = K - 1; j >= 0; --j) {
+            const float dj = dist[j];
+            const float dprev = (j > 0) ? dist[j - 1] : -kInf;
+            const int iprev = (j > 0) ? idx[j - 1] : -1;
+            const bool cprev = x < dprev;
+            const bool cj = x < dj;
+            dist[j] = cprev ? dprev : (cj ? x : dj);
+            idx[j] = cprev ? iprev : (cj ? id : idx[j]);
+        }
+    };
+
+    // B(Par(N_q)) terms: the ancestors whose leaves all sit in this wave
+    // (aligned sibling groups) contribute min D_p[k] + 2 lambda(ancestor)
+    // from the live lists; ancestors reaching outside the wave are left out
+    // of the minimum, which only loosens it.
+    const bool par_ok = a.leaf_list == nullptr && a.bound == KNN_BOUND_B;
+    float lam2_anc[6];
+#pragma unroll
+    for (int s = 1; s <= 5; ++s) {
+        // no such ancestor (shallow tree): the term is +inf
+        lam2_anc[s] = kInf;
+        if (par_ok && ((1 << lpl_log2) << (s - 1)) < 64 && has_leaf && ((qnode + 1) >> s) >= 1)
+            lam2_anc[s] = 2.0f * a.qlam[((qnode + 1) >> s) - 1];
+    }
+    lam2_anc[0] = lam2;
+
+    auto refresh_bound = [&]() {
+        if (a.bound == KNN_BOUND_NONE) return;
+        float hi = valid ? dist[K - 1] : -kInf;
+        float lo = valid ? dist[K - 1] : kInf;
+        for (int off = (1 << lpl_log2) >> 1; off > 0; off >>= 1) {
+            hi = fmaxf(hi, __shfl_xor(hi, off));
+            lo = fminf(lo, __shfl_xor(lo, off));
+        }
+        float b = hi;  // B1^2
+        if (a.bound == KNN_BOUND_B) {
+            const float b2 = sqrtf(lo) + lam2;
+            b = fminf(b, b2 * b2);
+            if (par_ok) {
+#pragma unroll
+                for (int s = 1; s <= 5; ++s) {
+                    const int off = (1 << lpl_log2) << (s - 1);
+                    if (off < 64) {
+                        lo = fminf(lo, __shfl_xor(lo, off));
+                        const float bp = sqrtf(lo) + lam2_anc[s];
+                        b = fminf(b, bp * bp);
+                    }
+                }
+            }
+        }
+        bound2 = fminf(b, seed2);
+    };
+
+    // BaseCase over one reference leaf: every lane against each reference
+    // point, CH points per batch.  A candidate must beat min(D_p[k], B):
+    // B bounds the point's final k-th distance, so anything farther cannot
+    // enter its final list (equal distances aside).
+    constexpr int CH = DP >= 32 ? 1 : 32 / DP;
+    auto tile = [&](int node) {
+        ++n_tiles;
+        const int2 rr = a.rrange[node];
+        const int base = uniform_i(rr.x);
+        const int cnt = uniform_i(rr.y);
+        const float *rp = a.rlpts + int64_t(node - a.r_first_leaf) * a.r_leaf_slots * DP;
+        n_pairs += uint64_t(cnt) * uint64_t(n_valid);
+        for (int t0 = 0; t0 < cnt; t0 += CH) {
+            float sd[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                float acc = 0.f;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const float df = q[j] - rp[(t0 + c) * DP + j];
+                    acc = fmaf(df, df, acc);
+                }
+                sd[c] = acc;
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const float lim = fminf(dist[K - 1], bound2 * kSlack);
+                const float thr = RESCORE ? lim * kGamma : lim;
+                const bool cand = valid && sd[c] < thr;
+                if (ballot(cand)) {
+                    ++n_pass;
+                    if (cand) {
+                        float x = sd[c];
+                        if (RESCORE) x = (float)d2_fp64<D>(q, rp + (t0 + c) * DP);
+                        if (x < dist[K - 1]) {
+                            insert(x, base + t0 + c);
+                            ++n_ins;
+                        }
+                    }
+                }
+            }
+        }
+        refresh_bound();
+    };
+
+    // ---- stackless depth-first walk, nearer child first ---------------------
+    {
+        float dm0, dm1;
+        int node = 0, depth = 0;
+        uint64_t nearbits = 0;
+        bool down = score(0, dm0);
+        if (down) {
+            for (;;) {
+                if (down) {
+                    if (node >= a.r_first_leaf) {
+                        tile(node);
+                        down = false;
+                        continue;
+                    }
+                    const int c0 = 2 * node + 1, c1 = c0 + 1;
+                    bool k0, k1;
+                    score_children(c0, k0, k1, dm0, dm1);
+                    if (!k0 && !k1) {
+                        down = false;
+                        continue;
+                    }
+                    const bool right = k1 && (!k0 || dm1 < dm0);
+                    if (right)
+                        nearbits |= (uint64_t(1) << depth);
+                    else
+                        nearbits &= ~(uint64_t(1) << depth);
+                    node = uniform_i(right ? c1 : c0);
+                    ++depth;
+                } else {
+                    if (node == 0) break;
+                    --depth;
+                    const bool is_right = (node & 1) == 0;
+                    const bool near_right = (nearbits >> depth) & 1;
+                    if (is_right == near_right) {
+                        const int far = is_right ? node - 1 : node + 1;
+                        if (score(far, dm0)) {
+                            node = far;
+                            ++depth;
+                            down = true;
+                            continue;
+                        }
+                    }
+                    node = uniform_i((node - 1) >> 1);
+                }
+            }
+        }
+    }
+
+    // ---- write-out: FP64 re-score of the final list, order by (d, index) ----
+    // Padding slots (below K-kk), unfilled slots and the query's own point
+    // get distinct keys that sort after every real entry, so real entries
+    // take ranks 0..k-1.
+    double e64[K];
+    int orig[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const bool real = valid && idx[j] >= 0 && !(a.self && idx[j] == qpos);
+        const int p = real ? idx[j] : 0;
+        e64[j] = real ? d2_fp64<D>(q, a.rpts + int64_t(p) * DP) : __builtin_inf();
+        orig[j] = real ? a.rperm[p] : 0x7fffffff - j;
+    }
+    double worst = -1.0;
+    if (valid) {
+        const int64_t row = int64_t(a.qperm[qpos]) * a.k;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            int rank = 0;
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                rank += (e64[i] < e64[j]) || (e64[i] == e64[j] && orig[i] < orig[j]);
+            if (rank < a.k) {
+                a.out_idx[row + rank] = orig[j] >= 0x7fffffff - K ? -1 : orig[j];
+                a.out_dist[row + rank] = (float)sqrt(e64[j]);
+                if (e64[j] != __builtin_inf()) worst = fmax(worst, e64[j]);
+            }
+        }
+    }
+    // largest k-th distance of the leaf, and the seed check: the leaf is
+    // exact when every point's k-th distance is within its seed radius
+    bool fb = false;
+    if (a.seed && valid) fb = !(dist[K - 1] <= seed2 * (1.0f - 0x1p-20f));
+    for (int off = (1 << lpl_log2) >> 1; off > 0; off >>= 1) {
+        worst = fmax(worst, __shfl_xor(worst, off));
+    }
+    const uint64_t fbmask = ballot(fb);
+    if (has_leaf && li == 0) {
+        if (a.leaf_kth) a.leaf_kth[qleaf] = (float)sqrt(fmax(worst, 0.0));
+        if (a.fallback) {
+            const int lpl = 1 << lpl_log2;
+            const uint64_t gm = (lpl == 64) ? ~0ull : (((1ull << lpl) - 1ull) << (g * lpl));
+            if (fbmask & gm) a.fallback[qleaf] = 1;
+        }
+    }
+    if (a.wave_log || a.stats) {
+        int ins = n_ins;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) ins += __shfl_xor(ins, off);
+        if (a.wave_log && lane == 0) {
+            uint32_t *w = a.wave_log + int64_t(wave) * 8;
+            w[0] = uint32_t(wall_clock64() - t_start);
+            w[1] = n_score;
+            w[2] = n_tiles;
+            w[3] = uint32_t(ins);
+            w[4] = n_pass;
+            w[5] = uint32_t(qleaf);
+        }
+        if (a.stats && lane == 0) {
+            atomicAdd(&a.stats[ST_SCORE], (unsigned long long)n_score);
+            atomicAdd(&a.stats[ST_TILES], (unsigned long long)n_tiles);
+            atomicAdd(&a.stats[ST_PAIRS], (unsigned long long)n_pairs);
+            atomicAdd(&a.stats[ST_INSERTS], (unsigned long long)ins);
+            atomicAdd(&a.stats[ST_FB_QUERIES], (unsigned long long)__popcll(fbmask));
+        }
+    }
+}
+
+template <int D>
+hipError_t launch_search_valu(const SearchArgs &a, int K, int grid, hipStream_t s) {
+    switch (K) {
+#define KNN_CASE(KK)                                                  \
+    case KK:                                                          \
+        k_search_valu<D, KK><<<grid, 256, 0, s>>>(a);                 \
+        break;
+        KNN_CASE(4)
+        KNN_CASE(5)
+        KNN_CASE(8)
+        KNN_CASE(11)
+        KNN_CASE(10)
+        KNN_CASE(16)
+        KNN_CASE(32)
+        KNN_CASE(50)
+        KNN_CASE(51)
+        KNN_CASE(64)
+#undef KNN_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace knnx

@@ -1,0 +1,261 @@
+"""ctypes binding of ``libknn_dualtree.so`` (C ABI in ``include/knn.h``).
+
+Argument marshalling only: torch CUDA tensors are passed as raw device
+pointers on the current HIP stream; every step of the search runs in the
+library's kernels.  Importing this module fails loudly when the library has
+not been built (``python -m paper_1304_4327_amd.build``); there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libknn_dualtree.so")
+
+KNN_OK = 0
+KNN_E_INVALID_ARG = 1
+KNN_E_NONFINITE = 2
+KNN_E_OOM = 3
+KNN_E_DEVICE = 4
+KNN_E_MODEL = 5
+KNN_E_UNSUPPORTED = 6
+
+KNN_BOUND_B = 0
+KNN_BOUND_B1 = 1
+KNN_BOUND_NONE = 2
+KNN_PREC_FP32 = 0
+KNN_PREC_BF16 = 1
+
+BOUNDS = {"B": KNN_BOUND_B, "B1": KNN_BOUND_B1, "none": KNN_BOUND_NONE}
+PRECISIONS = {"fp32": KNN_PREC_FP32, "bf16": KNN_PREC_BF16}
+
+
+class KnnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class knn_stats(ctypes.Structure):
+    _fields_ = [("score_calls", ctypes.c_int64), ("leaf_tiles", ctypes.c_int64),
+                ("pairs", ctypes.c_int64), ("inserts", ctypes.c_int64),
+                ("fallback_leaves", ctypes.c_int64), ("fallback_queries", ctypes.c_int64),
+                ("ms_query_build", ctypes.c_float), ("ms_search", ctypes.c_float),
+                ("ms_main_kernel", ctypes.c_float), ("n_query_leaves", ctypes.c_int32)]
+
+
+class knn_opts(ctypes.Structure):
+    _fields_ = [("bound", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("exclude_self", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("seed_radius", ctypes.c_void_p), ("leaf_kth_out", ctypes.c_void_p),
+                ("stats", ctypes.POINTER(knn_stats))]
+
+
+class knn_tree_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("dp", ctypes.c_int32),
+                ("leaf_size", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("n_nodes", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
+                ("first_leaf", ctypes.c_int64), ("points", ctypes.c_void_p),
+                ("perm", ctypes.c_void_p), ("node_range", ctypes.c_void_p),
+                ("box", ctypes.c_void_p), ("lambda_", ctypes.c_void_p),
+                ("split_dim", ctypes.c_void_p), ("ms_build", ctypes.c_float)]
+
+
+# every symbol include/knn.h declares, with (restype, argtypes)
+_P = ctypes.c_void_p
+_SIGS = {
+    "knn_opts_default": (None, [ctypes.POINTER(knn_opts)]),
+    "knn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "knn_last_error": (ctypes.c_char_p, []),
+    "knn_build_tree": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P,
+                                      ctypes.POINTER(_P)]),
+    "knn_free_tree": (None, [_P]),
+    "knn_tree_get_info": (ctypes.c_int, [_P, ctypes.POINTER(knn_tree_info)]),
+    "knn_search": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts), _P, _P, _P]),
+    "knn_search_points": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.POINTER(knn_opts), _P, _P, _P]),
+}
+
+_lib = None
+
+
+def load():
+    """Load the library (raises if it is missing: no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with "
+                              "`python -m paper_1304_4327_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status):
+    if status != KNN_OK:
+        msg = load().knn_last_error().decode()
+        raise KnnError(status, msg)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_f32(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.dim() != 2:
+        raise TypeError(f"{name} must be a contiguous 2-D float32 tensor")
+    return t
+
+
+class Tree:
+    """Owning wrapper of a ``knn_tree*`` handle."""
+
+    def __init__(self, handle, n, d):
+        self.handle = handle
+        self.n = n
+        self.d = d
+
+    def info(self):
+        return knn_tree_get_info(self)
+
+    def close(self):
+        if self.handle:
+            load().knn_free_tree(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def knn_build_tree(points, leaf_size: int, stream=None) -> Tree:
+    """Build a kd-tree over ``points`` (CUDA float32 [n, d])."""
+    if not hasattr(points, "is_cuda"):
+        raise TypeError("points must be a CUDA tensor")
+    _dev_f32(points, "points")
+    out = ctypes.c_void_p()
+    _check(load().knn_build_tree(ctypes.c_void_p(points.data_ptr()), points.shape[0],
+                                 points.shape[1], int(leaf_size), _stream(stream),
+                                 ctypes.byref(out)))
+    return Tree(out, points.shape[0], points.shape[1])
+
+
+def knn_tree_get_info(tree: Tree) -> dict:
+    info = knn_tree_info()
+    _check(load().knn_tree_get_info(tree.handle, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in knn_tree_info._fields_}
+
+
+def _make_opts(bound, precision, exclude_self, seed_radius, leaf_kth_out, stats):
+    o = knn_opts()
+    load().knn_opts_default(ctypes.byref(o))
+    o.bound = BOUNDS[bound] if isinstance(bound, str) else int(bound)
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.exclude_self = int(bool(exclude_self))
+    o.seed_radius = seed_radius.data_ptr() if seed_radius is not None else None
+    o.leaf_kth_out = leaf_kth_out.data_ptr() if leaf_kth_out is not None else None
+    st = knn_stats() if stats else None
+    o.stats = ctypes.pointer(st) if st is not None else None
+    return o, st
+
+
+def _stats_dict(st):
+    if st is None:
+        return None
+    return {f: getattr(st, f) for f, _ in knn_stats._fields_}
+
+
+def knn_search(ref: Tree, query: Tree | None, k: int, bound="B", precision="fp32",
+               exclude_self=False, seed_radius=None, leaf_kth_out=None, stats=False,
+               out=None, stream=None):
+    """k nearest neighbours of every query point (query None: ref on itself).
+
+    Returns (idx int64 [n_q, k], dist float32 [n_q, k], stats dict or None).
+    ``seed_radius``/``leaf_kth_out`` are CUDA float32 tensors with one entry
+    per query leaf.
+    """
+    torch = _torch()
+    nq = (query or ref).n
+    if out is None:
+        idx = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+        dist = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+    else:
+        idx, dist = out
+    o, st = _make_opts(bound, precision, exclude_self, seed_radius, leaf_kth_out, stats)
+    _check(load().knn_search(ref.handle, query.handle if query is not None else None, int(k),
+                             ctypes.byref(o), ctypes.c_void_p(idx.data_ptr()),
+                             ctypes.c_void_p(dist.data_ptr()), _stream(stream)))
+    return idx, dist, _stats_dict(st)
+
+
+def knn_search_points(ref: Tree, queries, k: int, bound="B", precision="fp32",
+                      seed_radius=None, leaf_kth_out=None, stats=False, out=None,
+                      stream=None):
+    """Build the query tree from ``queries`` (CUDA float32) and search."""
+    torch = _torch()
+    _dev_f32(queries, "queries")
+    nq = queries.shape[0]
+    if out is None:
+        idx = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+        dist = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+    else:
+        idx, dist = out
+    o, st = _make_opts(bound, precision, False, seed_radius, leaf_kth_out, stats)
+    _check(load().knn_search_points(ref.handle, ctypes.c_void_p(queries.data_ptr()), nq,
+                                    int(k), ctypes.byref(o), ctypes.c_void_p(idx.data_ptr()),
+                                    ctypes.c_void_p(dist.data_ptr()), _stream(stream)))
+    return idx, dist, _stats_dict(st)
+
+
+# ---------------------------------------------------------------------------
+# reading a tree's device arrays back (tests)
+# ---------------------------------------------------------------------------
+def _copy_dev(ptr, nbytes, dtype, shape):
+    torch = _torch()
+    t = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.restype = ctypes.c_int
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    torch.cuda.synchronize()
+    rc = hip.hipMemcpy(ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(ptr), nbytes, 3)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
+    return t.cpu().numpy().view(dtype).reshape(shape)
+
+
+def tree_arrays(tree: Tree) -> dict:
+    """Host copies of the tree's arrays (numpy)."""
+    i = knn_tree_get_info(tree)
+    n, dp, nn = i["n"], i["dp"], i["n_nodes"]
+    rng = _copy_dev(i["node_range"], nn * 8, np.int32, (nn, 2))
+    box = _copy_dev(i["box"], nn * 2 * dp * 4, np.float32, (nn, 2, dp))
+    return dict(
+        info=i,
+        points=_copy_dev(i["points"], (n + 64) * dp * 4, np.float32, (n + 64, dp)),
+        perm=_copy_dev(i["perm"], n * 4, np.int32, (n,)),
+        start=rng[:, 0], count=rng[:, 1],
+        lo=box[:, 0, :i["d"]], hi=box[:, 1, :i["d"]], box_pad=box[:, :, i["d"]:],
+        lam=_copy_dev(i["lambda_"], nn * 4, np.float32, (nn,)),
+        split_dim=_copy_dev(i["split_dim"], nn * 4, np.int32, (nn,)),
+    )

@@ -1,0 +1,68 @@
+"""The C-ABI library loads, exports every symbol include/knn.h declares,
+and rejects bad arguments before touching a device (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1304_4327_amd import knn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "knn.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(knn_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = knn.load()
+    names = _declared()
+    assert "knn_search" in names and "knn_build_tree" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) <= set(knn._SIGS), "binding lacks a declared symbol"
+
+
+def test_status_strings():
+    lib = knn.load()
+    assert lib.knn_status_string(0) == b"ok"
+    assert lib.knn_status_string(knn.KNN_E_INVALID_ARG) == b"invalid argument"
+
+
+def test_opts_default():
+    o = knn.knn_opts()
+    o.bound = 7
+    knn.load().knn_opts_default(ctypes.byref(o))
+    assert o.bound == knn.KNN_BOUND_B and o.precision == knn.KNN_PREC_FP32
+    assert not o.seed_radius and o.exclude_self == 0
+
+
+@pytest.mark.parametrize("n,d,leaf", [(0, 3, 8), (10, 0, 8), (10, 65, 8), (10, 3, 0),
+                                      (10, 3, 65), (-5, 3, 8)])
+def test_build_tree_rejects_bad_domain(n, d, leaf):
+    lib = knn.load()
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation comes first
+    st = lib.knn_build_tree(fake, n, d, leaf, None, ctypes.byref(out))
+    assert st == knn.KNN_E_INVALID_ARG
+    assert lib.knn_last_error()
+    assert not out.value
+
+
+def test_build_tree_rejects_null_points():
+    lib = knn.load()
+    out = ctypes.c_void_p()
+    assert lib.knn_build_tree(None, 10, 3, 8, None, ctypes.byref(out)) == knn.KNN_E_INVALID_ARG
+
+
+def test_search_rejects_null_tree():
+    lib = knn.load()
+    o = knn.knn_opts()
+    lib.knn_opts_default(ctypes.byref(o))
+    st = lib.knn_search(None, None, 3, ctypes.byref(o), ctypes.c_void_p(8), ctypes.c_void_p(8),
+                        None)
+    assert st == knn.KNN_E_INVALID_ARG
+    assert b"NULL" in lib.knn_last_error()

@@ -1,0 +1,141 @@
+"""GPU search vs the FP64 brute-force oracle, element by element, on seeded
+inputs shaped like the five workloads (shrunk so the oracle finishes in
+seconds, still many tiles and ragged leaves), plus edge cases."""
+import numpy as np
+import pytest
+
+from oracle import knn as ok
+from oracle import parity
+from paper_1304_4327_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _search(ref, q, k, leaf, bound="B", precision="fp32", leafq=None, stats=False, seed=None):
+    torch = _torch()
+    from paper_1304_4327_amd import knn
+    rt = knn.knn_build_tree(torch.from_numpy(ref).cuda(), leaf)
+    if q is None:
+        idx, dist, st = knn.knn_search(rt, None, k, bound=bound, precision=precision,
+                                       exclude_self=True, stats=stats, seed_radius=seed)
+    else:
+        qt = knn.knn_build_tree(torch.from_numpy(q).cuda(), leafq or leaf)
+        idx, dist, st = knn.knn_search(rt, qt, k, bound=bound, precision=precision, stats=stats,
+                                       seed_radius=seed)
+        qt.close()
+    rt.close()
+    torch.cuda.synchronize()
+    return idx.cpu().numpy(), dist.cpu().numpy(), st
+
+
+def _check(ref, q, k, gi, gd, rows=None):
+    self_mode = q is None
+    qq = ref if self_mode else q
+    if rows is None:
+        oi, od = ok.knn(qq, ref, k, exclude_self=self_mode)
+    else:
+        oi, od = ok.knn_rows(qq, rows, ref, k, exclude_self=self_mode)
+    return parity.assert_ok(qq, ref, k, gi, gd, oi, od, rows=rows, exclude_self=self_mode)
+
+
+def test_figure1_points():
+    P = np.array([[2, 2], [1, 2.5], [0.5, 0.5], [1, 3], [1.5, 2.5]], np.float32)
+    for k in (1, 2, 3, 4):
+        for leaf in (1, 2, 5):
+            gi, gd, _ = _search(P, None, k, leaf)
+            _check(P, None, k, gi, gd)
+    gi, gd, _ = _search(P, None, 4, 2)
+    assert gi[0].tolist() == [4, 1, 3, 2]
+    np.testing.assert_array_equal(gd[2], np.sqrt(np.float64([4.25, 4.5, 5.0, 6.5])).astype(np.float32))
+
+
+@pytest.mark.parametrize("bound", ["B", "B1", "none"])
+@pytest.mark.parametrize("leaf", [1, 2, 5, 20, 32, 64])
+def test_uniform10k_all_knn(bound, leaf):
+    ref, _, k, _ = datagen.make("uniform10k_d3_k5")
+    gi, gd, st = _search(ref, None, k, leaf, bound=bound, stats=True)
+    _check(ref, None, k, gi, gd)
+    if bound == "none":
+        # no pruning: every pair of the brute force (minus self pairs) is evaluated
+        assert st["pairs"] == len(ref) * len(ref)
+
+
+def test_bound_B_prunes_no_less_than_B1():
+    ref, _, k, leaf = datagen.make("uniform10k_d3_k5")
+    _, _, sb = _search(ref, None, k, leaf, bound="B", stats=True)
+    _, _, s1 = _search(ref, None, k, leaf, bound="B1", stats=True)
+    _, _, sn = _search(ref, None, k, leaf, bound="none", stats=True)
+    # B is a minimum that includes B1 (allow 1% for the different list
+    # evolution a tighter prune causes)
+    assert sb["pairs"] <= 1.01 * s1["pairs"]
+    assert s1["pairs"] < 0.2 * sn["pairs"]
+
+
+@pytest.mark.parametrize("name,scale", [("gmm1m_d3_k10", 0.02), ("zipfgmm2m_d8_k10", 0.005),
+                                        ("manifold4m_d16_k10", 0.005),
+                                        ("manifold1m_d64_k50", 0.01)])
+def test_workload_shapes(name, scale):
+    ref, q, k, leaf = datagen.make(name, scale=scale)
+    gi, gd, _ = _search(ref, q, k, leaf)
+    _check(ref, q, k, gi, gd)
+
+
+@pytest.mark.parametrize("k", [6, 18, 26])
+def test_lattice_ties(k):
+    g = datagen.lattice(12, 3)
+    gi, gd, _ = _search(g, None, k, 8)
+    _check(g, None, k, gi, gd)
+    inner = np.all((g >= 1) & (g <= 10), axis=1)
+    shell = {6: 1.0, 18: 2.0, 26: 3.0}[k]
+    np.testing.assert_array_equal(gd[inner, -1], np.float32(np.sqrt(shell)))
+
+
+def test_duplicates_reported_at_zero():
+    rng = np.random.default_rng(3)
+    ref = rng.random((2000, 3)).astype(np.float32)
+    ref[1000:1100] = ref[5]
+    gi, gd, _ = _search(ref, None, 4, 16)
+    _check(ref, None, 4, gi, gd)
+    assert np.all(gd[1000:1100, 0] == 0)
+
+
+@pytest.mark.parametrize("m,k", [(2, 1), (9, 8), (70, 64), (300, 1), (300, 64)])
+def test_k_edges(m, k):
+    rng = np.random.default_rng(m + k)
+    ref = rng.random((m, 4)).astype(np.float32)
+    q = rng.random((37, 4)).astype(np.float32)
+    gi, gd, _ = _search(ref, q, k, 4)
+    _check(ref, q, k, gi, gd)
+
+
+def test_single_query_and_separate_leaf_sizes():
+    rng = np.random.default_rng(9)
+    ref = rng.random((5000, 3)).astype(np.float32)
+    q = rng.random((1, 3)).astype(np.float32)
+    gi, gd, _ = _search(ref, q, 7, 32)
+    _check(ref, q, 7, gi, gd)
+    q = rng.random((999, 3)).astype(np.float32)
+    gi, gd, _ = _search(ref, q, 7, 32, leafq=5)
+    _check(ref, q, 7, gi, gd)
+
+
+def test_deterministic():
+    ref, q, k, leaf = datagen.make("gmm1m_d3_k10", scale=0.01)
+    a = _search(ref, q, k, leaf)
+    b = _search(ref, q, k, leaf)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_k_too_large_rejected():
+    torch = _torch()
+    from paper_1304_4327_amd import knn
+    ref = np.random.default_rng(0).random((10, 3)).astype(np.float32)
+    rt = knn.knn_build_tree(torch.from_numpy(ref).cuda(), 4)
+    with pytest.raises(knn.KnnError) as e:
+        knn.knn_search(rt, None, 10, exclude_self=True)
+    assert e.value.status == knn.KNN_E_INVALID_ARG
