@@ -43,6 +43,14 @@ hipError_t launch_valu(const SearchArgs &a, int d, int K, int grid, hipStream_t 
     }
 }
 
+hipError_t launch_mfma(const SearchArgs &a, int dp, int K, int grid, hipStream_t s) {
+    switch (dp) {
+        case 16: return launch_search_mfma_dp16(a, K, grid, s);
+        case 32: return launch_search_mfma_dp32(a, K, grid, s);
+        default: return launch_search_mfma_dp64(a, K, grid, s);
+    }
+}
+
 __global__ void k_compact_fallback(const int *__restrict__ flag, int n, int *__restrict__ list,
                                    int *__restrict__ count) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -90,8 +98,6 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     if (opts.precision < 0 || opts.precision > 1)
         return fail(KNN_E_INVALID_ARG, "knn_search: bad precision");
     if (opts.reserved != 0) return fail(KNN_E_INVALID_ARG, "knn_search: reserved field must be 0");
-    if (opts.precision == KNN_PREC_BF16)
-        return fail(KNN_E_UNSUPPORTED, "knn_search: BF16 tiles are not built into this library");
 
     if (opts.exclude_self && k > 63)
         return fail(KNN_E_INVALID_ARG, "knn_search: need k <= 63 with exclude_self");
@@ -100,6 +106,14 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     int lpl_log2 = 0;
     while ((1 << lpl_log2) < max_leaf) ++lpl_log2;
     if (qt->dp >= 32) lpl_log2 = 6;
+    const bool bf16 = opts.precision == KNN_PREC_BF16;
+    if (bf16) {
+        if (ref->dp < 16)
+            return fail(KNN_E_UNSUPPORTED, "knn_search: BF16 tiles need d >= 9 (a 16-wide k-step)");
+        if (max_leaf > 32 || ref->leaf_slots > 32)
+            return fail(KNN_E_UNSUPPORTED, "knn_search: BF16 tiles need leaves of <= 32 points");
+        lpl_log2 = 6;  // one query leaf per wave
+    }
     const int NG = 64 >> lpl_log2;
     const int nq_leaves = int(qt->n_leaves);
 
@@ -166,7 +180,7 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
         }
     } eg{ev};
     KNN_HIP(hipEventRecord(ev[0], s));
-    KNN_HIP(launch_valu(a, ref->d, K, grid, s));
+    KNN_HIP(bf16 ? launch_mfma(a, ref->dp, K, grid, s) : launch_valu(a, ref->d, K, grid, s));
     KNN_HIP(hipEventRecord(ev[1], s));
     if (opts.seed_radius) {
         k_compact_fallback<<<(nq_leaves + 255) / 256, 256, 0, s>>>(fb_flag, nq_leaves, fb_list,
@@ -177,7 +191,7 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
         b.leaf_list = fb_list;
         b.n_list_dev = fb_count;
         b.wave_log = nullptr;
-        KNN_HIP(launch_valu(b, ref->d, K, grid, s));
+        KNN_HIP(bf16 ? launch_mfma(b, ref->dp, K, grid, s) : launch_valu(b, ref->d, K, grid, s));
     }
     KNN_HIP(hipEventRecord(ev[2], s));
     unsigned long long hst[ST_COUNT] = {};

@@ -60,6 +60,11 @@ hipError_t launch_search_valu_d16(const SearchArgs &a, int K, int grid, hipStrea
 hipError_t launch_search_valu_d32(const SearchArgs &a, int K, int grid, hipStream_t s);
 hipError_t launch_search_valu_d64(const SearchArgs &a, int K, int grid, hipStream_t s);
 
+// BF16 MFMA kernels (search_mfma_d*.hip), stride 16, 32 or 64
+hipError_t launch_search_mfma_dp16(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_mfma_dp32(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_mfma_dp64(const SearchArgs &a, int K, int grid, hipStream_t s);
+
 // compile-time list lengths; a request for a list of kk entries (k, or k+1
 // when the query's own point shares the list) uses the smallest K >= kk
 constexpr int kListSizes[] = {4, 5, 8, 10, 11, 16, 32, 50, 51, 64};

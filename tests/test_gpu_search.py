@@ -139,3 +139,43 @@ def test_k_too_large_rejected():
     with pytest.raises(knn.KnnError) as e:
         knn.knn_search(rt, None, 10, exclude_self=True)
     assert e.value.status == knn.KNN_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("name,scale", [("manifold4m_d16_k10", 0.005), ("manifold1m_d64_k50", 0.01)])
+@pytest.mark.parametrize("bound", ["B", "B1"])
+def test_bf16_tiles_match_oracle(name, scale, bound):
+    """BF16 MFMA tiles with the proven margin and FP64 re-score: the same
+    exact answer as the oracle."""
+    ref, q, k, leaf = datagen.make(name, scale=scale)
+    gi, gd, st = _search(ref, q, k, leaf, bound=bound, precision="bf16", stats=True)
+    _check(ref, q, k, gi, gd)
+
+
+@pytest.mark.parametrize("d,k", [(9, 1), (16, 7), (33, 20), (64, 64)])
+def test_bf16_dims_and_self(d, k):
+    rng = np.random.default_rng(d * 100 + k)
+    ref = (rng.standard_normal((3000, d)) * rng.uniform(0.1, 3.0, d)).astype(np.float32)
+    ref[100:140] = ref[7]          # duplicates: zero distances, ties
+    kk = min(k, 63)
+    gi, gd, _ = _search(ref, None, kk, 16, precision="bf16")
+    _check(ref, None, kk, gi, gd)
+    q = rng.standard_normal((500, d)).astype(np.float32)
+    gi, gd, _ = _search(ref, q, k, 32, precision="bf16")
+    _check(ref, q, k, gi, gd)
+
+
+def test_bf16_same_answer_as_fp32():
+    ref, q, k, leaf = datagen.make("manifold4m_d16_k10", scale=0.004)
+    a = _search(ref, q, k, leaf, precision="fp32")
+    b = _search(ref, q, k, leaf, precision="bf16")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_bf16_low_dim_unsupported():
+    torch = _torch()
+    from paper_1304_4327_amd import knn
+    ref = np.random.default_rng(0).random((100, 3)).astype(np.float32)
+    rt = knn.knn_build_tree(torch.from_numpy(ref).cuda(), 8)
+    with pytest.raises(knn.KnnError) as e:
+        knn.knn_search(rt, None, 3, exclude_self=True, precision="bf16")
+    assert e.value.status == knn.KNN_E_UNSUPPORTED
