@@ -48,6 +48,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learned", action="store_true",
+                    help="train the seed network on 8 other seeded draws of the workload "
+                         "(untimed), then time steps that include seed inference")
+    ap.add_argument("--train-epochs", type=int, default=20)
+    ap.add_argument("--compare", action="store_true",
+                    help="also time the plain FP32 path on the same workload and report "
+                         "the speedup of the chosen variant over it")
     return ap.parse_args()
 
 
@@ -96,40 +103,72 @@ def main():
     dist = torch.empty((nq, k), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
-    def step():
+    model = None
+    train_info = None
+    if args.learned:
+        from paper_1304_4327_amd import seed as S
+        base = datagen.DEFAULT_SEEDS[args.workload]
+        train_seeds = list(range(40, 48)) if args.workload == "zipfgmm2m_d8_k10" else \
+            [base + 100 + i for i in range(8)]
+        t0 = time.perf_counter()
+        model = S.train_for_workload(args.workload, train_seeds, epochs=args.train_epochs)
+        train_info = {"train_seeds": train_seeds, "eval_seed": base,
+                      "train_s": time.perf_counter() - t0, "log_margin": model.log_margin,
+                      "loss_first": model.history[0], "loss_last": model.history[-1]}
+
+    def step(precision, learned=False):
         rt = knn.knn_build_tree(R, leaf, stream=stream)
-        if self_mode:
-            _, _, st = knn.knn_search(rt, None, k, bound=args.bound, precision=args.precision,
-                                      exclude_self=True, stats=True, out=(idx, dist),
-                                      stream=stream)
-            st["ms_ref_build"] = rt.info()["ms_build"]
-        else:
-            qt = knn.knn_build_tree(Q, leaf, stream=stream)
-            _, _, st = knn.knn_search(rt, qt, k, bound=args.bound, precision=args.precision,
-                                      stats=True, out=(idx, dist), stream=stream)
-            st["ms_ref_build"] = rt.info()["ms_build"]
+        qt = None if self_mode else knn.knn_build_tree(Q, leaf, stream=stream)
+        rad = None
+        if learned:
+            from paper_1304_4327_amd import seed as S
+            rad = S.radii(model, knn.knn_seed_features(rt, qt, stream=stream))
+        _, _, st = knn.knn_search(rt, qt, k, bound=args.bound, precision=precision,
+                                  exclude_self=self_mode, stats=True, out=(idx, dist),
+                                  seed_radius=rad, stream=stream)
+        st["ms_ref_build"] = rt.info()["ms_build"]
+        if qt is not None:
             st["ms_query_build"] = qt.info()["ms_build"]
             qt.close()
         rt.close()
         return st
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        stats.append(step())
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
+    def timed(precision, steps, warmup, learned=False):
+        for _ in range(warmup):
+            step(precision, learned)
+        torch.cuda.synchronize()
+        sts = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sts.append(step(precision, learned))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, sts
+
+    total, stats = timed(args.precision, args.steps, args.warmup, args.learned)
     ms_step = total / args.steps * 1e3
     value = nq * args.steps / total
+    compare = None
+    if args.compare:
+        base_total, base_stats = timed("fp32", max(1, min(args.steps, 2)), 1)
+        base_ms = base_total / max(1, min(args.steps, 2)) * 1e3
+        compare = {"baseline": "plain FP32 dual-tree (same workload, same bound)",
+                   "baseline_ms_per_step": base_ms, "variant_ms_per_step": ms_step,
+                   "speedup": base_ms / ms_step,
+                   "baseline_pairs_per_query": float(np.mean([s["pairs"] for s in base_stats])) / nq}
 
     kern_ms = float(np.mean([s["ms_main_kernel"] for s in stats]))
     pairs = float(np.mean([s["pairs"] for s in stats]))
-    flop_per_pair = 3 * d - 1
+    if args.precision == "bf16":
+        # BF16 MFMA: 2 d flops per pair on the matrix cores (padded k-steps
+        # of 16 count as issued work, the algorithmic count uses d)
+        flop_per_pair = 2 * d
+        peak = PEAKS["bf16_mfma_tflops"]
+        bound_kind, kname = "mfma", "k_search_mfma"
+    else:
+        flop_per_pair = 3 * d - 1
+        peak = PEAKS["fp32_vector_tflops"]
+        bound_kind, kname = "alu", "k_search_valu"
     achieved = pairs * flop_per_pair / (kern_ms * 1e-3) / 1e12
-    peak = PEAKS["fp32_vector_tflops"]
     traffic = TRAFFIC_BYTES_PER_LAUNCH.get((args.workload, args.precision))
     line = {
         "metric": "exact kNN queries/s, 1M\u00d71M d=3 k=10; learned+BF16 vs plain FP32 speedup",
@@ -142,14 +181,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16+f64" if args.precision == "bf16" else "f32",
         "data": "synthetic (seeded, generated on the host; no dataset)",
         "config": {"workload": args.workload, "n_ref": len(ref), "n_query": nq, "d": d, "k": k,
                    "leaf_size": leaf, "bound": args.bound, "precision": args.precision,
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                   "learned_seed": bool(args.learned), "parallelism": "single GPU"},
+        "roofline": {"bound": bound_kind, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "k_search_valu", "kernel_ms": kern_ms,
+                     "kernel": kname, "kernel_ms": kern_ms,
                      "flop_per_pair": flop_per_pair, "pairs_per_launch": pairs},
         "breakdown_ms": {
             "ref_build": float(np.mean([s["ms_ref_build"] for s in stats])),
@@ -159,6 +198,17 @@ def main():
         "pairs_per_query": pairs / nq,
         "score_calls": float(np.mean([s["score_calls"] for s in stats])),
     }
+    if compare:
+        line["compare"] = compare
+    if args.learned:
+        line["learned"] = dict(train_info,
+                               fallback_leaves=float(np.mean([s["fallback_leaves"] for s in stats])),
+                               fallback_queries=float(np.mean([s["fallback_queries"] for s in stats])),
+                               query_leaves=stats[0]["n_query_leaves"],
+                               fallback_query_rate=float(np.mean([s["fallback_queries"] for s in stats])) / nq,
+                               fallback_pairs_per_query=float(np.mean([s["fallback_pairs"] for s in stats])) / nq,
+                               ms_seeded_pass=float(np.mean([s["ms_main_kernel"] for s in stats])),
+                               ms_search_total=float(np.mean([s["ms_search"] for s in stats])))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ref, q, k, self_mode, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -81,6 +81,8 @@ typedef struct knn_stats {
     float ms_search;          /* device time, traversal incl. fallback           */
     float ms_main_kernel;     /* device time of the main traversal launch        */
     int32_t n_query_leaves;   /* leaves of the query tree                        */
+    int64_t fallback_pairs;   /* pairs evaluated by the fallback pass (included
+                                 in `pairs`)                                     */
 } knn_stats;
 
 typedef struct knn_opts {
@@ -176,6 +178,57 @@ knn_status knn_search(const knn_tree *ref, const knn_tree *query, int32_t k,
 knn_status knn_search_points(const knn_tree *ref, const float *queries, int64_t n_q,
                              int32_t k, const knn_opts *opts, int64_t *idx_out,
                              float *dist_out, void *stream);
+
+
+/* ------------------------------------------------------------------------
+ * Learned seed radius (not part of the paper; it only supplies the initial
+ * value of a query leaf's bound, see knn_opts.seed_radius).
+ * Network: n_in -> 64 -> 64 -> 1, ReLU, FP32 weights, inputs standardised
+ * inside the network as (x - mu) * inv_sd.  Parameters travel as one flat
+ * FP32 vector: W1 (64 x n_in, row-major), b1 (64), W2 (64 x 64), b2 (64),
+ * w3 (64), b3 (1).  All compute runs in the library's kernels; every call
+ * synchronises its stream.
+ * ------------------------------------------------------------------------ */
+typedef struct knn_mlp knn_mlp;
+
+/* New network with all parameters 0, mu = 0, inv_sd = 1, y_mu = 0, y_sd = 1.
+ * Domain: 1 <= n_in <= 72; hidden must be 64 (else KNN_E_UNSUPPORTED). */
+knn_status knn_mlp_create(int32_t n_in, int32_t hidden, knn_mlp **out);
+void knn_mlp_free(knn_mlp *mlp);
+knn_status knn_mlp_num_params(const knn_mlp *mlp, int64_t *n);
+/* host <-> device parameter copies (n must equal the parameter count);
+ * set_params also clears the Adam moments and step counter */
+knn_status knn_mlp_set_params(knn_mlp *mlp, const float *host, int64_t n);
+knn_status knn_mlp_get_params(const knn_mlp *mlp, float *host, int64_t n);
+/* gradient of the last knn_mlp_loss_grad call */
+knn_status knn_mlp_get_grads(const knn_mlp *mlp, float *host, int64_t n);
+/* input standardisation (host arrays of n_in) and the output scale used by
+ * knn_seed_radius: log radius = y * y_sd + y_mu */
+knn_status knn_mlp_set_norm(knn_mlp *mlp, const float *mu_host, const float *inv_sd_host,
+                            float y_mu, float y_sd);
+/* y[i] = network output for x[i] (device, x: n x n_in, y: n) */
+knn_status knn_mlp_forward(const knn_mlp *mlp, const float *x, int64_t n, float *y, void *stream);
+/* L = (1/n) sum (y_i - t_i)^2 over the batch (device x: n x n_in, t: n);
+ * stores dL/dparams in the network and *loss_host = L (if not NULL) */
+knn_status knn_mlp_loss_grad(knn_mlp *mlp, const float *x, const float *t, int64_t n,
+                             float *loss_host, void *stream);
+/* one Adam step (bias-corrected) with the stored gradient */
+knn_status knn_mlp_adam_step(knn_mlp *mlp, float lr, float beta1, float beta2, float eps,
+                             void *stream);
+/* versioned binary file: magic, sizes, output scale, mu, inv_sd, params */
+knn_status knn_mlp_save(const knn_mlp *mlp, const char *path);
+knn_status knn_mlp_load(const char *path, knn_mlp **out);
+
+/* Per query leaf (n_leaves x (d + 3), device): its box centre (d values),
+ * lambda, point count, and log(count / volume) of the reference leaf reached
+ * by descending from the root toward that centre (volume of the tight box,
+ * each extent clamped below at 1e-6 of the root's extent).  query == NULL:
+ * the reference tree's own leaves. */
+knn_status knn_seed_features(const knn_tree *ref, const knn_tree *query, float *feats,
+                             void *stream);
+/* radius[i] = exp(net(feats[i]) * y_sd + y_mu + log_margin), device arrays */
+knn_status knn_seed_radius(const knn_mlp *mlp, const float *feats, int64_t n, float log_margin,
+                           float *radius, void *stream);
 
 #ifdef __cplusplus
 }

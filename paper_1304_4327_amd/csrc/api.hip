@@ -51,10 +51,9 @@ hipError_t launch_mfma(const SearchArgs &a, int dp, int K, int grid, hipStream_t
     }
 }
 
-__global__ void k_compact_fallback(const int *__restrict__ flag, int n, int *__restrict__ list,
-                                   int *__restrict__ count) {
+__global__ void k_count_flags(const int *__restrict__ flag, int n, int *__restrict__ count) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && flag[i]) list[atomicAdd(count, 1)] = i;
+    if (i < n && flag[i]) atomicAdd(count, 1);
 }
 
 struct Scratch {
@@ -120,13 +119,14 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     Scratch sc{s, {}};
     unsigned long long *dstats = nullptr;
     if (opts.stats) {
-        KNN_HIP(sc.get(&dstats, ST_COUNT));
-        KNN_HIP(hipMemsetAsync(dstats, 0, ST_COUNT * sizeof(unsigned long long), s));
+        KNN_HIP(sc.get(&dstats, 2 * ST_COUNT));
+        KNN_HIP(hipMemsetAsync(dstats, 0, 2 * ST_COUNT * sizeof(unsigned long long), s));
     }
-    int *fb_flag = nullptr, *fb_list = nullptr, *fb_count = nullptr;
+    int *fb_flag = nullptr, *fb_count = nullptr;
+    float *fb_bound = nullptr;
     if (opts.seed_radius) {
+        KNN_HIP(sc.get(&fb_bound, nq_leaves));
         KNN_HIP(sc.get(&fb_flag, nq_leaves));
-        KNN_HIP(sc.get(&fb_list, nq_leaves));
         KNN_HIP(sc.get(&fb_count, 1));
         KNN_HIP(hipMemsetAsync(fb_flag, 0, nq_leaves * sizeof(int), s));
         KNN_HIP(hipMemsetAsync(fb_count, 0, sizeof(int), s));
@@ -147,8 +147,7 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     a.qlam = qt->lam;
     a.q_first_leaf = int(qt->first_leaf);
     a.q_n_leaves = nq_leaves;
-    a.leaf_list = nullptr;
-    a.n_list_dev = nullptr;
+    a.active = nullptr;
     a.d = ref->d;
     a.k = k;
     a.lpl_log2 = lpl_log2;
@@ -159,6 +158,7 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     a.out_dist = dist_out;
     a.leaf_kth = opts.leaf_kth_out;
     a.fallback = fb_flag;
+    a.fb_bound = fb_bound;
     a.stats = dstats;
     // debug aid: KNN_WAVE_LOG=<file> writes per-wave counters of the main launch
     const char *wlog_path = std::getenv("KNN_WAVE_LOG");
@@ -183,18 +183,20 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     KNN_HIP(bf16 ? launch_mfma(a, ref->dp, K, grid, s) : launch_valu(a, ref->d, K, grid, s));
     KNN_HIP(hipEventRecord(ev[1], s));
     if (opts.seed_radius) {
-        k_compact_fallback<<<(nq_leaves + 255) / 256, 256, 0, s>>>(fb_flag, nq_leaves, fb_list,
-                                                                   fb_count);
+        k_count_flags<<<(nq_leaves + 255) / 256, 256, 0, s>>>(fb_flag, nq_leaves, fb_count);
+        // fallback: the listed leaves again, from empty lists, with the
+        // proven bound of the first pass as their initial bound
         SearchArgs b = a;
-        b.seed = nullptr;
+        b.seed = fb_bound;
         b.fallback = nullptr;
-        b.leaf_list = fb_list;
-        b.n_list_dev = fb_count;
+        b.fb_bound = nullptr;
+        b.active = fb_flag;
+        b.stats = dstats ? dstats + ST_COUNT : nullptr;  // counted separately
         b.wave_log = nullptr;
         KNN_HIP(bf16 ? launch_mfma(b, ref->dp, K, grid, s) : launch_valu(b, ref->d, K, grid, s));
     }
     KNN_HIP(hipEventRecord(ev[2], s));
-    unsigned long long hst[ST_COUNT] = {};
+    unsigned long long hst[2 * ST_COUNT] = {};
     int hfb = 0;
     if (dstats)
         KNN_HIP(hipMemcpyAsync(hst, dstats, sizeof(hst), hipMemcpyDeviceToHost, s));
@@ -210,11 +212,13 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     }
     if (opts.stats) {
         knn_stats *st = opts.stats;
-        st->score_calls = int64_t(hst[ST_SCORE]);
-        st->leaf_tiles = int64_t(hst[ST_TILES]);
-        st->pairs = int64_t(hst[ST_PAIRS]);
-        st->inserts = int64_t(hst[ST_INSERTS]);
+        const unsigned long long *f = hst + ST_COUNT;
+        st->score_calls = int64_t(hst[ST_SCORE] + f[ST_SCORE]);
+        st->leaf_tiles = int64_t(hst[ST_TILES] + f[ST_TILES]);
+        st->pairs = int64_t(hst[ST_PAIRS] + f[ST_PAIRS]);
+        st->inserts = int64_t(hst[ST_INSERTS] + f[ST_INSERTS]);
         st->fallback_queries = int64_t(hst[ST_FB_QUERIES]);
+        st->fallback_pairs = int64_t(f[ST_PAIRS]);
         st->fallback_leaves = hfb;
         (void)hipEventElapsedTime(&st->ms_main_kernel, ev[0], ev[1]);
         (void)hipEventElapsedTime(&st->ms_search, ev[0], ev[2]);

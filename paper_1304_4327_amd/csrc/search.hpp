@@ -32,10 +32,9 @@ struct SearchArgs {
     const float *qlam;
     int q_first_leaf;
     int q_n_leaves;
-    // work list: query leaves to process.  leaf_list == NULL means all
-    // leaves 0..q_n_leaves-1; otherwise *n_list_dev entries.
-    const int *leaf_list;
-    const int *n_list_dev;
+    // leaves to process: active == NULL means all; otherwise only leaves
+    // with active[leaf] != 0 (the waves keep their sibling-aligned leaves)
+    const int *active;
     int d, k, lpl_log2;
     int bound;          // knn_bound
     int self;           // exclude reference position == query position
@@ -44,6 +43,9 @@ struct SearchArgs {
     float *out_dist;
     float *leaf_kth;    // per query leaf, or NULL
     int *fallback;      // per query leaf flag (seeded runs), or NULL
+    float *fb_bound;    // per query leaf (seeded runs): a proven bound for the
+                        // fallback pass, min D_p[k] + 2 lambda over the leaf's
+                        // queries with a full list (+inf if none), or NULL
     unsigned long long *stats;  // ST_COUNT counters, or NULL
     uint32_t *wave_log;         // debug: 8 words per wave (ticks, scores, tiles, inserts, passes, leaf)
 };

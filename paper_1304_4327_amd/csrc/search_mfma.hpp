@@ -79,9 +79,10 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
     const int wslot = threadIdx.x >> 6;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int wave = blk * 4 + wslot;
-    const int n_list = a.leaf_list ? *a.n_list_dev : a.q_n_leaves;
+    const int n_list = a.q_n_leaves;
     if (wave >= n_list) return;
-    const int qleaf = uniform_i(a.leaf_list ? a.leaf_list[wave] : wave);
+    if (a.active && a.active[wave] == 0) return;
+    const int qleaf = uniform_i(wave);
     const int qnode = a.q_first_leaf + qleaf;
     const int2 qr = a.qrange[qnode];
     const int qcount = uniform_i(qr.y);
@@ -370,9 +371,15 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
 #pragma unroll
     for (int off = 16; off > 0; off >>= 1) lw = fmaxf(lw, __shfl_xor(lw, off));
     const uint64_t fbmask = ballot(fb);
+    float fbb = (valid && worst < kInf) ? worst : kInf;
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) fbb = fminf(fbb, __shfl_xor(fbb, off));
     if (lane == 0) {
         if (a.leaf_kth) a.leaf_kth[qleaf] = fmaxf(lw, 0.0f);
-        if (a.fallback && fbmask) a.fallback[qleaf] = 1;
+        if (a.fallback && fbmask) {
+            a.fallback[qleaf] = 1;
+            if (a.fb_bound) a.fb_bound[qleaf] = fbb < kInf ? (fbb + lam2) * (1.0f + 0x1p-20f) : kInf;
+        }
     }
     if (a.wave_log || a.stats) {
         int ins = n_ins;

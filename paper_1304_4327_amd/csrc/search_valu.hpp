@@ -83,12 +83,13 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     const int wave = blk * 4 + (threadIdx.x >> 6);
     const int lpl_log2 = a.lpl_log2;
     const int NG = 64 >> lpl_log2;
-    const int n_list = a.leaf_list ? *a.n_list_dev : a.q_n_leaves;
+    const int n_list = a.q_n_leaves;
     if (wave * NG >= n_list) return;
     const int g = lane >> lpl_log2, li = lane & ((1 << lpl_log2) - 1);
     const int slot = wave * NG + g;
-    const bool has_leaf = slot < n_list;
-    const int qleaf = has_leaf ? (a.leaf_list ? a.leaf_list[slot] : slot) : 0;
+    const bool has_leaf = slot < n_list && (!a.active || a.active[slot] != 0);
+    if (!ballot(has_leaf)) return;
+    const int qleaf = has_leaf ? slot : 0;
     const int qnode = a.q_first_leaf + qleaf;
     const int2 qr = has_leaf ? a.qrange[qnode] : make_int2(0, 0);
     const bool valid = has_leaf && li < qr.y;
@@ -96,15 +97,21 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     const int kk = a.k + (a.self ? 1 : 0);  // list length (self match included)
 
     float q[D];
-    // union box of the wave's query leaves: every lane holds the same
-    // values, so the visit-order key computed from it is wave-uniform
-    float ulo[D], uhi[D];
     {
         const float *qp = a.qpts + int64_t(valid ? qpos : 0) * DP;
+#pragma unroll
+        for (int j = 0; j < D; ++j) q[j] = valid ? qp[j] : 0.f;
+    }
+    // union box of the wave's query leaves, for the wave-uniform visit-order
+    // key.  Low d: every lane holds the whole box.  High d: lane l holds
+    // dimension l of it (the key is then summed across lanes).
+    constexpr bool WIDE = D >= 16;
+    constexpr int UD = WIDE ? 1 : D;
+    float ulo[UD], uhi[UD];
+    if constexpr (!WIDE) {
         const float *qb = a.qbox + int64_t(has_leaf ? qnode : 0) * 2 * DP;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            q[j] = valid ? qp[j] : 0.f;
             float lo = has_leaf ? qb[j] : kInf;
             float hi = has_leaf ? qb[DP + j] : -kInf;
             for (int off = (1 << lpl_log2); off < 64; off <<= 1) {
@@ -114,6 +121,18 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
             ulo[j] = lo;
             uhi[j] = hi;
         }
+    } else {
+        float lo = lane < DP ? kInf : 0.f, hi = lane < DP ? -kInf : 0.f;
+        for (int gg = 0; gg < NG; ++gg) {
+            const int sl = wave * NG + gg;
+            if (sl < n_list && (!a.active || a.active[sl] != 0) && lane < DP) {
+                const float *qb = a.qbox + int64_t(a.q_first_leaf + sl) * 2 * DP;
+                lo = fminf(lo, qb[lane]);
+                hi = fmaxf(hi, qb[DP + lane]);
+            }
+        }
+        ulo[0] = lo;
+        uhi[0] = hi;
     }
     const float lam2 = has_leaf ? 2.0f * a.qlam[qnode] : 0.f;
     // a seed is only a pruning radius; NaN or negative values prune
@@ -142,16 +161,25 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     // the box is within its bound; the visit-order key is the wave-uniform
     // d_min^2 between the union of the wave's leaf boxes and the node's box
     auto score_box = [&](const float *b, float &key_out) -> bool {
-        float s = 0.f, u = 0.f;
+        float sd = 0.f, u = 0.f;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             const float lo = b[j], hi = b[DP + j];
             const float gap = fmaxf(fmaxf(lo - q[j], q[j] - hi), 0.0f);
-            s = fmaf(gap, gap, s);
-            const float ug = fmaxf(fmaxf(lo - uhi[j], ulo[j] - hi), 0.0f);
-            u = fmaf(ug, ug, u);
+            sd = fmaf(gap, gap, sd);
+            if constexpr (!WIDE) {
+                const float ug = fmaxf(fmaxf(lo - uhi[j], ulo[j] - hi), 0.0f);
+                u = fmaf(ug, ug, u);
+            }
         }
-        const bool keep = valid && !(s > point_bound2() * kSlack);
+        if constexpr (WIDE) {
+            const float lo = lane < DP ? b[lane] : 0.f, hi = lane < DP ? b[DP + lane] : 0.f;
+            const float ug = fmaxf(fmaxf(lo - uhi[0], ulo[0] - hi), 0.0f);
+            u = ug * ug;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off);
+        }
+        const bool keep = valid && !(sd > point_bound2() * kSlack);
         key_out = uniform_f(u);
         return ballot(keep) != 0;
     };
@@ -184,7 +212,7 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     // (aligned sibling groups) contribute min D_p[k] + 2 lambda(ancestor)
     // from the live lists; ancestors reaching outside the wave are left out
     // of the minimum, which only loosens it.
-    const bool par_ok = a.leaf_list == nullptr && a.bound == KNN_BOUND_B;
+    const bool par_ok = a.bound == KNN_BOUND_B;
     float lam2_anc[6];
 #pragma unroll
     for (int s = 1; s <= 5; ++s) {
@@ -316,19 +344,18 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     }
 
     // ---- write-out: FP64 re-score of the final list, order by (d, index) ----
-    // Padding slots (below K-kk), unfilled slots and the query's own point
-    // get distinct keys that sort after every real entry, so real entries
-    // take ranks 0..k-1.
-    double e64[K];
-    int orig[K];
+    // Each entry becomes its output key in place: the FP32 distance from the
+    // FP64 re-score and the original index.  Padding slots (below K-kk),
+    // unfilled slots and the query's own point get distinct +inf keys that
+    // rank after every real entry, so real entries take ranks 0..k-1.
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const bool real = valid && idx[j] >= 0 && !(a.self && idx[j] == qpos);
         const int p = real ? idx[j] : 0;
-        e64[j] = real ? d2_fp64<D>(q, a.rpts + int64_t(p) * DP) : __builtin_inf();
-        orig[j] = real ? a.rperm[p] : 0x7fffffff - j;
+        dist[j] = real ? (float)sqrt(d2_fp64<D>(q, a.rpts + int64_t(p) * DP)) : kInf;
+        idx[j] = real ? a.rperm[p] : 0x7fffffff - j;
     }
-    double worst = -1.0;
+    float worst = -1.0f;
     if (valid) {
         const int64_t row = int64_t(a.qperm[qpos]) * a.k;
 #pragma unroll
@@ -336,28 +363,35 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
             int rank = 0;
 #pragma unroll
             for (int i = 0; i < K; ++i)
-                rank += (e64[i] < e64[j]) || (e64[i] == e64[j] && orig[i] < orig[j]);
+                rank += (dist[i] < dist[j]) || (dist[i] == dist[j] && idx[i] < idx[j]);
             if (rank < a.k) {
-                a.out_idx[row + rank] = orig[j] >= 0x7fffffff - K ? -1 : orig[j];
-                a.out_dist[row + rank] = (float)sqrt(e64[j]);
-                if (e64[j] != __builtin_inf()) worst = fmax(worst, e64[j]);
+                a.out_idx[row + rank] = idx[j] >= 0x7fffffff - K ? -1 : idx[j];
+                a.out_dist[row + rank] = dist[j];
+                if (rank == a.k - 1) worst = dist[j];
             }
         }
     }
     // largest k-th distance of the leaf, and the seed check: the leaf is
     // exact when every point's k-th distance is within its seed radius
     bool fb = false;
-    if (a.seed && valid) fb = !(dist[K - 1] <= seed2 * (1.0f - 0x1p-20f));
+    if (a.seed && valid) fb = !((double)worst * worst <= (double)seed2 * (1.0 - 0x1p-20));
+    // a proven bound for the fallback pass: min over full lists of D_p[k]
+    // plus 2 lambda (the B2 argument holds whatever seed built the lists)
+    float fbb = (valid && worst < kInf) ? worst : kInf;
     for (int off = (1 << lpl_log2) >> 1; off > 0; off >>= 1) {
-        worst = fmax(worst, __shfl_xor(worst, off));
+        worst = fmaxf(worst, __shfl_xor(worst, off));
     }
     const uint64_t fbmask = ballot(fb);
+    for (int off = (1 << lpl_log2) >> 1; off > 0; off >>= 1) fbb = fminf(fbb, __shfl_xor(fbb, off));
     if (has_leaf && li == 0) {
-        if (a.leaf_kth) a.leaf_kth[qleaf] = (float)sqrt(fmax(worst, 0.0));
+        if (a.leaf_kth) a.leaf_kth[qleaf] = fmaxf(worst, 0.0f);
         if (a.fallback) {
             const int lpl = 1 << lpl_log2;
             const uint64_t gm = (lpl == 64) ? ~0ull : (((1ull << lpl) - 1ull) << (g * lpl));
-            if (fbmask & gm) a.fallback[qleaf] = 1;
+            if (fbmask & gm) {
+                a.fallback[qleaf] = 1;
+                if (a.fb_bound) a.fb_bound[qleaf] = fbb < kInf ? (fbb + lam2) * (1.0f + 0x1p-20f) : kInf;
+            }
         }
     }
     if (a.wave_log || a.stats) {

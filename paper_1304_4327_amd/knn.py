@@ -45,7 +45,8 @@ class knn_stats(ctypes.Structure):
                 ("pairs", ctypes.c_int64), ("inserts", ctypes.c_int64),
                 ("fallback_leaves", ctypes.c_int64), ("fallback_queries", ctypes.c_int64),
                 ("ms_query_build", ctypes.c_float), ("ms_search", ctypes.c_float),
-                ("ms_main_kernel", ctypes.c_float), ("n_query_leaves", ctypes.c_int32)]
+                ("ms_main_kernel", ctypes.c_float), ("n_query_leaves", ctypes.c_int32),
+                ("fallback_pairs", ctypes.c_int64)]
 
 
 class knn_opts(ctypes.Structure):
@@ -78,6 +79,22 @@ _SIGS = {
     "knn_search": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts), _P, _P, _P]),
     "knn_search_points": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32,
                                          ctypes.POINTER(knn_opts), _P, _P, _P]),
+    "knn_mlp_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "knn_mlp_free": (None, [_P]),
+    "knn_mlp_num_params": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "knn_mlp_set_params": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    "knn_mlp_get_params": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    "knn_mlp_get_grads": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    "knn_mlp_set_norm": (ctypes.c_int, [_P, _P, _P, ctypes.c_float, ctypes.c_float]),
+    "knn_mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
+    "knn_mlp_loss_grad": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_float), _P]),
+    "knn_mlp_adam_step": (ctypes.c_int, [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_float, _P]),
+    "knn_mlp_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "knn_mlp_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_P)]),
+    "knn_seed_features": (ctypes.c_int, [_P, _P, _P, _P]),
+    "knn_seed_radius": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_float, _P, _P]),
 }
 
 _lib = None
@@ -259,3 +276,98 @@ def tree_arrays(tree: Tree) -> dict:
         lam=_copy_dev(i["lambda_"], nn * 4, np.float32, (nn,)),
         split_dim=_copy_dev(i["split_dim"], nn * 4, np.int32, (nn,)),
     )
+
+
+# ---------------------------------------------------------------------------
+# seed network
+# ---------------------------------------------------------------------------
+class Mlp:
+    """Owning wrapper of a ``knn_mlp*`` (n_in -> 64 -> 64 -> 1 network)."""
+
+    def __init__(self, n_in: int | None = None, handle=None):
+        if handle is None:
+            h = ctypes.c_void_p()
+            _check(load().knn_mlp_create(int(n_in), 64, ctypes.byref(h)))
+            handle = h
+        self.handle = handle
+        n = ctypes.c_int64()
+        _check(load().knn_mlp_num_params(self.handle, ctypes.byref(n)))
+        self.n_params = n.value
+
+    @classmethod
+    def load_file(cls, path: str) -> "Mlp":
+        h = ctypes.c_void_p()
+        _check(load().knn_mlp_load(path.encode(), ctypes.byref(h)))
+        return cls(handle=h)
+
+    def save(self, path: str):
+        _check(load().knn_mlp_save(self.handle, path.encode()))
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(load().knn_mlp_set_params(self.handle, p.ctypes.data, p.size))
+
+    def get_params(self):
+        p = np.empty(self.n_params, np.float32)
+        _check(load().knn_mlp_get_params(self.handle, p.ctypes.data, p.size))
+        return p
+
+    def get_grads(self):
+        g = np.empty(self.n_params, np.float32)
+        _check(load().knn_mlp_get_grads(self.handle, g.ctypes.data, g.size))
+        return g
+
+    def set_norm(self, mu, inv_sd, y_mu=0.0, y_sd=1.0):
+        mu = np.ascontiguousarray(mu, dtype=np.float32)
+        isd = np.ascontiguousarray(inv_sd, dtype=np.float32)
+        _check(load().knn_mlp_set_norm(self.handle, mu.ctypes.data, isd.ctypes.data,
+                                       float(y_mu), float(y_sd)))
+
+    def forward(self, x, stream=None):
+        torch = _torch()
+        y = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
+        _check(load().knn_mlp_forward(self.handle, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                      ctypes.c_void_p(y.data_ptr()), _stream(stream)))
+        return y
+
+    def loss_grad(self, x, t, stream=None) -> float:
+        loss = ctypes.c_float()
+        _check(load().knn_mlp_loss_grad(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(t.data_ptr()), x.shape[0],
+                                        ctypes.byref(loss), _stream(stream)))
+        return loss.value
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(load().knn_mlp_adam_step(self.handle, float(lr), float(beta1), float(beta2),
+                                        float(eps), _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            load().knn_mlp_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def knn_seed_features(ref: Tree, query: Tree | None, stream=None):
+    """(n_query_leaves, d + 3) float32 CUDA tensor of seed features."""
+    torch = _torch()
+    qt = query or ref
+    nl = knn_tree_get_info(qt)["n_leaves"]
+    f = torch.empty((nl, ref.d + 3), dtype=torch.float32, device="cuda")
+    _check(load().knn_seed_features(ref.handle, query.handle if query is not None else None,
+                                    ctypes.c_void_p(f.data_ptr()), _stream(stream)))
+    return f
+
+
+def knn_seed_radius(mlp: Mlp, feats, log_margin: float = 0.0, stream=None):
+    torch = _torch()
+    r = torch.empty(feats.shape[0], dtype=torch.float32, device="cuda")
+    _check(load().knn_seed_radius(mlp.handle, ctypes.c_void_p(feats.data_ptr()), feats.shape[0],
+                                  float(log_margin), ctypes.c_void_p(r.data_ptr()),
+                                  _stream(stream)))
+    return r

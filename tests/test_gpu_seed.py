@@ -1,0 +1,154 @@
+"""Learned seed radius on the GPU: network kernels vs the FP64 reference,
+features vs the oracle, exactness under any seed, and the gain of a
+trained network over the plain search."""
+import numpy as np
+import pytest
+
+from oracle import kdtree as okd
+from oracle import knn as ok
+from oracle import mlp as omlp
+from oracle import parity
+from oracle import seed_features as osf
+from paper_1304_4327_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _net(n_in, seed):
+    from paper_1304_4327_amd import knn
+    rng = np.random.default_rng(seed)
+    p = datagen.mlp_init(n_in, 64, seed)
+    p[64 * n_in:64 * n_in + 64] = rng.normal(0, 0.1, 64)     # non-zero biases
+    mu = rng.normal(size=n_in).astype(np.float32)
+    isd = rng.uniform(0.5, 2.0, n_in).astype(np.float32)
+    net = knn.Mlp(n_in)
+    net.set_params(p)
+    net.set_norm(mu, isd)
+    return net, p.astype(np.float64), mu.astype(np.float64), isd.astype(np.float64)
+
+
+@pytest.mark.parametrize("n_in,n", [(11, 1), (11, 1000), (19, 333), (67, 257)])
+def test_forward_and_gradient_match_fp64(n_in, n):
+    torch = _torch()
+    net, p, mu, isd = _net(n_in, n_in + n)
+    rng = np.random.default_rng(n)
+    x = rng.normal(size=(n, n_in)).astype(np.float32)
+    t = rng.normal(size=n).astype(np.float32)
+    X, T = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    y = net.forward(X).cpu().numpy()
+    y64 = omlp.forward(p, x, mu, isd, n_in, 64)
+    np.testing.assert_allclose(y, y64, rtol=1e-4, atol=1e-5 * np.abs(y64).max())
+    loss = net.loss_grad(X, T)
+    L64, g64 = omlp.loss_and_grad(p, x, t, mu, isd, n_in, 64)
+    assert abs(loss - L64) <= 1e-4 * L64
+    g = net.get_grads()
+    scale = np.abs(g64).max()
+    assert np.all(np.abs(g - g64) <= 1e-4 * (np.abs(g64) + 1e-3 * scale))
+
+
+def test_adam_steps_match_fp64():
+    torch = _torch()
+    n_in, n = 11, 500
+    net, p, mu, isd = _net(n_in, 5)
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=(n, n_in)).astype(np.float32)
+    t = rng.normal(size=n).astype(np.float32)
+    X, T = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for step in range(1, 4):
+        net.loss_grad(X, T)
+        net.adam_step(1e-3)
+        _, g = omlp.loss_and_grad(p, x, t, mu, isd, n_in, 64)
+        p, m, v = omlp.adam_step(p, g, m, v, step, 1e-3)
+    got = net.get_params()
+    assert np.all(np.abs(got - p) <= 2e-6 + 1e-5 * np.abs(p))
+
+
+def test_save_load_roundtrip(tmp_path):
+    from paper_1304_4327_amd import knn
+    net, p, mu, isd = _net(11, 2)
+    f = str(tmp_path / "net.knnseed")
+    net.save(f)
+    back = knn.Mlp.load_file(f)
+    np.testing.assert_array_equal(back.get_params(), net.get_params())
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"not a model")
+    with pytest.raises(knn.KnnError) as e:
+        knn.Mlp.load_file(str(bad))
+    assert e.value.status == knn.KNN_E_MODEL
+
+
+def test_seed_features_match_oracle():
+    torch = _torch()
+    from paper_1304_4327_amd import knn
+    ref, q, k, leaf = datagen.make("zipfgmm2m_d8_k10", scale=0.004)
+    rt = knn.knn_build_tree(torch.from_numpy(ref).cuda(), leaf)
+    qt = knn.knn_build_tree(torch.from_numpy(q).cuda(), leaf)
+    f = knn.knn_seed_features(rt, qt).cpu().numpy().astype(np.float64)
+    o = osf.features(okd.build(ref, leaf), okd.build(q, leaf))
+    d = ref.shape[1]
+    np.testing.assert_array_equal(f[:, :d], o[:, :d])            # centres
+    np.testing.assert_array_equal(f[:, d + 1], o[:, d + 1])      # counts
+    assert np.all(f[:, d] >= o[:, d]) and np.all(f[:, d] <= o[:, d] * (1 + 3e-7))
+    np.testing.assert_allclose(f[:, d + 2], o[:, d + 2], rtol=1e-5, atol=1e-4)
+
+
+def _seeded(ref, q, k, leaf, seed_fn, precision="fp32"):
+    torch = _torch()
+    from paper_1304_4327_amd import knn
+    rt = knn.knn_build_tree(torch.from_numpy(ref).cuda(), leaf)
+    qt = knn.knn_build_tree(torch.from_numpy(q).cuda(), leaf)
+    nl = qt.info()["n_leaves"]
+    seed = seed_fn(nl)
+    s = None if seed is None else torch.from_numpy(seed.astype(np.float32)).cuda()
+    idx, dist, st = knn.knn_search(rt, qt, k, precision=precision, seed_radius=s, stats=True)
+    return idx.cpu().numpy(), dist.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("kind", ["zero", "inf", "random", "nan", "negative"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_any_seed_gives_the_plain_answer(kind, precision):
+    name = "zipfgmm2m_d8_k10" if precision == "fp32" else "manifold4m_d16_k10"
+    ref, q, k, leaf = datagen.make(name, scale=0.003)
+    plain = _seeded(ref, q, k, leaf, lambda n: None, precision)
+    rng = np.random.default_rng(1)
+    fn = {"zero": lambda n: np.zeros(n), "inf": lambda n: np.full(n, np.inf),
+          "random": lambda n: rng.exponential(plain[1][:, -1].mean(), n),
+          "nan": lambda n: np.full(n, np.nan), "negative": lambda n: -np.ones(n)}[kind]
+    got = _seeded(ref, q, k, leaf, fn, precision)
+    assert np.array_equal(got[0], plain[0]) and np.array_equal(got[1], plain[1])
+    if kind in ("zero", "nan", "negative"):
+        assert got[2]["fallback_leaves"] == got[2]["n_query_leaves"]
+    if kind == "inf":
+        assert got[2]["fallback_leaves"] == 0
+
+
+def test_trained_seed_prunes_more_and_stays_exact():
+    """Train on 8 seeded draws of the Zipf-GMM workload (scaled down), then
+    on a held-out draw: the seeded search returns the oracle's answer with
+    fewer pair evaluations than the plain search."""
+    torch = _torch()
+    from paper_1304_4327_amd import knn, seed as S
+    scale = 0.01
+    model = S.train_for_workload("zipfgmm2m_d8_k10", range(40, 48), scale=scale, epochs=15)
+    assert model.history[-1] < model.history[0]
+    ref, q, k, leaf = datagen.make("zipfgmm2m_d8_k10", seed=48, scale=scale)
+    rt = knn.knn_build_tree(torch.from_numpy(ref).cuda(), leaf)
+    qt = knn.knn_build_tree(torch.from_numpy(q).cuda(), leaf)
+    _, _, plain = knn.knn_search(rt, qt, k, stats=True)
+    feats = knn.knn_seed_features(rt, qt)
+    rad = S.radii(model, feats)
+    idx, dist, st = knn.knn_search(rt, qt, k, seed_radius=rad, stats=True)
+    rows = np.arange(0, len(q), 7)
+    oi, od = ok.knn_rows(q, rows, ref, k)
+    parity.assert_ok(q, ref, k, idx.cpu().numpy(), dist.cpu().numpy(), oi, od, rows=rows)
+    assert st["fallback_leaves"] < 0.5 * st["n_query_leaves"]
+    # the seeded pass itself prunes more than the plain search; the total
+    # (with the fallback pass) is reported by the benchmark
+    assert st["pairs"] - st["fallback_pairs"] < plain["pairs"]
