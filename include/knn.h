@@ -22,6 +22,10 @@
  *   - Opaque handles (knn_tree, knn_mlp) own device memory on the device that
  *     was current when they were created; free them with the matching
  *     *_free call.
+ *   - Trees and per-call scratch use a caching allocator: released blocks
+ *     stay with the process and are reused in stream order (a block released
+ *     on one stream and taken on another makes the new stream wait for the
+ *     release).  knn_release_cached_memory() hands them back to the device.
  */
 #ifndef KNN_DUALTREE_H
 #define KNN_DUALTREE_H
@@ -108,6 +112,13 @@ void knn_opts_default(knn_opts *opts);
 const char *knn_status_string(knn_status s);
 /* Description of the last error on the calling thread ("" if none). */
 const char *knn_last_error(void);
+
+/* Returns every cached (released, unused) device block of every device to
+ * the runtime.  Waits for the work queued before each block's release.
+ * Blocks still owned by live trees are not affected.  Errors: KNN_E_DEVICE. */
+knn_status knn_release_cached_memory(void);
+/* Bytes currently held in the cache (released, not yet reused). */
+int64_t knn_cached_bytes(void);
 
 /* ------------------------------------------------------------------------
  * kd-tree (Section "Space Trees", Definition 1; kd-tree bounds paragraph).

@@ -255,6 +255,15 @@ const char *knn_status_string(knn_status s) {
 
 const char *knn_last_error(void) { return get_error(); }
 
+knn_status knn_release_cached_memory(void) {
+    hipError_t e = release_cached();
+    if (e != hipSuccess)
+        return fail(KNN_E_DEVICE, std::string("knn_release_cached_memory: ") + hipGetErrorString(e));
+    return KNN_OK;
+}
+
+int64_t knn_cached_bytes(void) { return int64_t(cached_bytes()); }
+
 knn_status knn_build_tree(const float *points, int64_t n, int32_t d, int32_t leaf_size,
                           void *stream, knn_tree **out) {
     set_error("");

@@ -56,6 +56,8 @@ struct knn_tree {
     float *lam = nullptr;         // n_nodes
     int32_t *split_dim = nullptr; // n_nodes
     int device = 0;
+    hipStream_t stream = nullptr;  // stream the tree was built on; its memory is
+                                   // released in order on this stream
     float ms_build = 0.f;
 };
 
@@ -95,13 +97,16 @@ knn_status build_tree(const float *points, int64_t n, int d, int leaf, hipStream
                       knn_tree **out);
 void free_tree(knn_tree *t);
 
-// stream-ordered scratch allocation
+// Device memory for trees and scratch comes from the library's caching
+// allocator (memory.hip): stream-ordered reuse of released blocks.
+hipError_t dev_alloc(void **p, size_t bytes, hipStream_t s);
+void dev_free(void *p, hipStream_t s);
+hipError_t release_cached();
+size_t cached_bytes();
 template <class T>
 inline hipError_t alloc_async(T **p, size_t count, hipStream_t s) {
-    return hipMallocAsync(reinterpret_cast<void **>(p), count * sizeof(T) + 256, s);
+    return dev_alloc(reinterpret_cast<void **>(p), count * sizeof(T) + 256, s);
 }
-inline void free_async(void *p, hipStream_t s) {
-    if (p) (void)hipFreeAsync(p, s);
-}
+inline void free_async(void *p, hipStream_t s) { dev_free(p, s); }
 
 }  // namespace knnx

@@ -11,10 +11,12 @@
 //   children keep ascending original-index order (stable partition).
 //
 // Level-synchronous construction:
-//   * levels whose segments exceed kLocalMax points run as grid-wide passes:
-//     segmented box reduction, radix select (4 x 8-bit digits of an
-//     order-preserving uint32 key) of the median key per segment, and a
-//     stable partition by a segmented scan of (less, equal) counts;
+//   * levels whose segments exceed kLocalMax points run as grid-wide passes
+//     over a copy of the points kept in the current order (coalesced reads;
+//     each partition moves the rows along with their indices): segmented box
+//     reduction, radix select (11 + 11 + 10-bit digits of an order-preserving
+//     uint32 key) of the median key per segment, and a stable partition by a
+//     segmented scan of (less, equal) counts;
 //   * the remaining levels of every segment of <= kLocalMax points are built
 //     by one wavefront in LDS (same select/partition, wave ballots instead of
 //     block scans).
@@ -30,7 +32,7 @@ namespace knnx {
 namespace {
 
 constexpr int kLocalMax = 1024;  // segments this small finish in one wave
-constexpr int kChunk = 4096;     // elements per block in grid-wide levels
+constexpr int kChunk = 1024;     // elements per block in grid-wide levels
 constexpr int kBlock = 256;
 
 struct Sel {
@@ -60,35 +62,61 @@ __global__ void k_ranges(int2 *range, int n, int n_nodes) {
     range[i] = make_int2(start, cnt);
 }
 
-__global__ void k_iota(int *a, int n) {
+
+__global__ void k_fill_box(uint32_t *a, int n, int dp) {
+    // layout [seg][2][dp]: lo words start all-ones, hi words zero
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = i;
+    if (i < n) a[i] = ((i / dp) & 1) ? 0u : 0xffffffffu;
 }
 
-__global__ void k_fill_u32(uint32_t *a, int n, uint32_t lo_val, uint32_t hi_val, int dp) {
-    // boxu layout: [seg][2][dp]; first half of each seg = lo (init lo_val)
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = ((i / dp) & 1) ? hi_val : lo_val;
-}
-
-// ---- grid-wide level: box ---------------------------------------------------
+// ---- initial copy: padded rows in input order, non-finite check -------------
 template <int DP>
-__global__ __launch_bounds__(kBlock) void k_box_level(const float *__restrict__ P, int d,
-                                                      const int *__restrict__ idx,
-                                                      const int2 *__restrict__ range,
-                                                      int node0, int bps,
-                                                      uint32_t *__restrict__ boxu) {
+__global__ void k_init(const float *__restrict__ P, int64_t n, int d, float *__restrict__ cur,
+                       int *__restrict__ idx, int *__restrict__ flag) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t row = t / DP;
+    const int j = int(t % DP);
+    if (row >= n + kPadRows) return;
+    float v = 0.f;
+    if (row < n) {
+        if (j == 0) idx[row] = int(row);
+        if (j < d) {
+            v = P[row * d + j];
+            if (!isfinite(v)) atomicOr(flag, 1);
+        }
+    }
+    cur[t] = v;
+}
+
+// ---- grid-wide level: box -----------------------------------------------------
+template <int DP>
+__global__ __launch_bounds__(kBlock) void k_box_level(const float *__restrict__ cur, int d,
+                                                      const int2 *__restrict__ range, int node0,
+                                                      int bps, uint32_t *__restrict__ boxu) {
     const int seg = blockIdx.x / bps, chunk = blockIdx.x % bps;
     const int2 r = range[node0 + seg];
     const int e0 = chunk * kChunk, e1 = min(r.y, e0 + kChunk);
     const int t = threadIdx.x, j = t % DP, grp = t / DP;
     constexpr int NG = kBlock / DP;
+    constexpr int IT = kChunk / NG;  // elements per thread
+    constexpr int BATCH = IT < 16 ? IT : 16;  // loads issued together
     uint32_t lo = 0xffffffffu, hi = 0u;
     if (j < d) {
-        for (int e = e0 + grp; e < e1; e += NG) {
-            uint32_t k = f2key(P[int64_t(idx[r.x + e]) * d + j]);
-            lo = min(lo, k);
-            hi = max(hi, k);
+        for (int q0 = 0; q0 < IT; q0 += BATCH) {
+            float v[BATCH];
+#pragma unroll
+            for (int q = 0; q < BATCH; ++q) {
+                const int e = e0 + grp + (q0 + q) * NG;
+                v[q] = e < e1 ? cur[int64_t(r.x + e) * DP + j] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < BATCH; ++q) {
+                if (e0 + grp + (q0 + q) * NG < e1) {
+                    const uint32_t k = f2key(v[q]);
+                    lo = min(lo, k);
+                    hi = max(hi, k);
+                }
+            }
         }
     }
 #pragma unroll
@@ -113,11 +141,13 @@ __global__ __launch_bounds__(kBlock) void k_box_level(const float *__restrict__ 
     }
 }
 
+// per segment: write the node box, pick the split dimension, reset the
+// accumulators for the next level, start the rank search
 template <int DP>
-__global__ void k_box_finalize(const uint32_t *__restrict__ boxu, const int2 *__restrict__ range,
+__global__ void k_box_finalize(uint32_t *__restrict__ boxu, const int2 *__restrict__ range,
                                int node0, int nseg, int d, float *__restrict__ box,
                                int *__restrict__ split_dim, Sel *__restrict__ sel) {
-    int seg = blockIdx.x * blockDim.x + threadIdx.x;
+    const int seg = blockIdx.x * blockDim.x + threadIdx.x;
     if (seg >= nseg) return;
     const int node = node0 + seg;
     const int2 r = range[node];
@@ -130,7 +160,7 @@ __global__ void k_box_finalize(const uint32_t *__restrict__ boxu, const int2 *__
             if (r.y > 0) {
                 lo = key2f(boxu[(seg * 2) * DP + j]);
                 hi = key2f(boxu[(seg * 2 + 1) * DP + j]);
-                float ext = hi - lo;
+                const float ext = hi - lo;
                 if (ext > bestext) {
                     bestext = ext;
                     best = j;
@@ -142,15 +172,20 @@ __global__ void k_box_finalize(const uint32_t *__restrict__ boxu, const int2 *__
         }
         b[j] = lo;
         b[DP + j] = hi;
+        boxu[(seg * 2) * DP + j] = 0xffffffffu;
+        boxu[(seg * 2 + 1) * DP + j] = 0u;
     }
     split_dim[node] = best;
     sel[seg] = Sel{0u, 0u, r.y / 2, 0};
 }
 
-// ---- grid-wide level: radix select of the median key ----------------------
+// ---- grid-wide level: radix select of the median key, 3 digits of 11 bits ----
+constexpr int kDigitBits = 11, kBins = 1 << kDigitBits;
+__host__ __device__ constexpr int digit_shift(int pass) { return pass == 0 ? 21 : pass == 1 ? 10 : 0; }
+__host__ __device__ constexpr uint32_t digit_mask(int pass) { return pass == 2 ? 0x3ffu : 0x7ffu; }
+
 template <int DP>
-__global__ __launch_bounds__(kBlock) void k_hist(const float *__restrict__ P, int d,
-                                                 const int *__restrict__ idx,
+__global__ __launch_bounds__(kBlock) void k_hist(const float *__restrict__ cur,
                                                  const int2 *__restrict__ range, int node0,
                                                  int bps, const int *__restrict__ split_dim,
                                                  uint32_t *__restrict__ keys,
@@ -160,72 +195,92 @@ __global__ __launch_bounds__(kBlock) void k_hist(const float *__restrict__ P, in
     const int node = node0 + seg;
     const int2 r = range[node];
     const int e0 = chunk * kChunk, e1 = min(r.y, e0 + kChunk);
-    const int j = split_dim[node];
     const Sel s = sel[seg];
-    const int shift = 24 - 8 * pass;
-    __shared__ int h[256];
-    h[threadIdx.x] = 0;
+    const int shift = digit_shift(pass);
+    const uint32_t dm = digit_mask(pass);
+    __shared__ int h[kBins];
+    for (int i = threadIdx.x; i < kBins; i += kBlock) h[i] = 0;
     __syncthreads();
-    for (int e = e0 + threadIdx.x; e < e1; e += kBlock) {
-        uint32_t key;
-        if (pass == 0) {
-            key = f2key(P[int64_t(idx[r.x + e]) * d + j]);
-            keys[r.x + e] = key;
-        } else {
-            key = keys[r.x + e];
-        }
-        if ((key & s.mask) == s.prefix) atomicAdd(&h[(key >> shift) & 255u], 1);
-    }
-    __syncthreads();
-    int c = h[threadIdx.x];
-    if (c) atomicAdd(&hist[seg * 256 + threadIdx.x], c);
-}
-
-// one wave per segment: pick the digit holding the wanted rank
-__global__ __launch_bounds__(64) void k_select(int *__restrict__ hist, Sel *__restrict__ sel,
-                                               const int2 *__restrict__ range, int node0,
-                                               int pass) {
-    const int seg = blockIdx.x, lane = threadIdx.x;
-    const int shift = 24 - 8 * pass;
-    int *h = hist + seg * 256;
-    int h0 = h[lane * 4 + 0], h1 = h[lane * 4 + 1], h2 = h[lane * 4 + 2], h3 = h[lane * 4 + 3];
-    int s = h0 + h1 + h2 + h3;
-    int incl = s;
+    constexpr int IT = kChunk / kBlock;
+    uint32_t kv[IT];
+    if (pass == 0) {
+        const int j = split_dim[node];
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int v = __shfl_up(incl, off);
-        if (lane >= off) incl += v;
-    }
-    const int excl = incl - s;
-    Sel st = sel[seg];
-    const bool live = range[node0 + seg].y > 0;
-    const bool mine = live && excl <= st.rank && st.rank < incl;
-    if (mine) {
-        int rem = st.rank - excl, bin = lane * 4;
-        if (rem >= h0) {
-            rem -= h0;
-            ++bin;
-            if (rem >= h1) {
-                rem -= h1;
-                ++bin;
-                if (rem >= h2) {
-                    rem -= h2;
-                    ++bin;
-                }
+        for (int q = 0; q < IT; ++q) {
+            const int e = e0 + threadIdx.x + q * kBlock;
+            kv[q] = e < e1 ? f2key(cur[int64_t(r.x + e) * DP + j]) : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < IT; ++q) {
+            const int e = e0 + threadIdx.x + q * kBlock;
+            if (e < e1) {
+                keys[r.x + e] = kv[q];
+                atomicAdd(&h[kv[q] >> shift], 1);
             }
         }
+    } else {
+#pragma unroll
+        for (int q = 0; q < IT; ++q) {
+            const int e = e0 + threadIdx.x + q * kBlock;
+            kv[q] = e < e1 ? keys[r.x + e] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < IT; ++q) {
+            const int e = e0 + threadIdx.x + q * kBlock;
+            if (e < e1 && (kv[q] & s.mask) == s.prefix) atomicAdd(&h[(kv[q] >> shift) & dm], 1);
+        }
+    }
+    __syncthreads();
+    int *gh = hist + int64_t(seg) * kBins;
+    for (int i = threadIdx.x; i < kBins; i += kBlock)
+        if (h[i]) atomicAdd(&gh[i], h[i]);
+}
+
+// one block per segment: the digit holding the wanted rank; clears the bins
+__global__ __launch_bounds__(kBlock) void k_select(int *__restrict__ hist, Sel *__restrict__ sel,
+                                                   const int2 *__restrict__ range, int node0,
+                                                   int pass) {
+    const int seg = blockIdx.x;
+    const int shift = digit_shift(pass);
+    const uint32_t dm = digit_mask(pass);
+    int *gh = hist + int64_t(seg) * kBins;
+    constexpr int PER = kBins / kBlock;  // 8 bins per thread
+    int c[PER], sum = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        c[q] = gh[threadIdx.x * PER + q];
+        gh[threadIdx.x * PER + q] = 0;
+        sum += c[q];
+    }
+    __shared__ int sc[kBlock];
+    sc[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const int v = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
+        __syncthreads();
+        sc[threadIdx.x] += v;
+        __syncthreads();
+    }
+    const int incl = sc[threadIdx.x], excl = incl - sum;
+    const Sel s0 = sel[seg];
+    if (range[node0 + seg].y > 0 && excl <= s0.rank && s0.rank < incl) {
+        int rem = s0.rank - excl, bin = threadIdx.x * PER;
+#pragma unroll
+        for (int q = 0; q < PER - 1; ++q) {
+            if (rem >= c[q] && bin == threadIdx.x * PER + q) {
+                rem -= c[q];
+                ++bin;
+            }
+        }
+        Sel st = s0;
         st.prefix |= uint32_t(bin) << shift;
-        st.mask |= 255u << shift;
+        st.mask |= dm << shift;
         st.rank = rem;
         sel[seg] = st;
     }
-    h[lane * 4 + 0] = 0;
-    h[lane * 4 + 1] = 0;
-    h[lane * 4 + 2] = 0;
-    h[lane * 4 + 3] = 0;
 }
 
-// ---- grid-wide level: stable partition ---------------------------------------
+// ---- grid-wide level: stable partition -----------------------------------------
 __global__ __launch_bounds__(kBlock) void k_part_count(const uint32_t *__restrict__ keys,
                                                        const int2 *__restrict__ range,
                                                        int node0, int bps,
@@ -236,10 +291,15 @@ __global__ __launch_bounds__(kBlock) void k_part_count(const uint32_t *__restric
     const int e0 = chunk * kChunk, e1 = min(r.y, e0 + kChunk);
     const uint32_t v = sel[seg].prefix;
     int nl = 0, ne = 0;
-    for (int e = e0 + threadIdx.x; e < e1; e += kBlock) {
-        uint32_t key = keys[r.x + e];
-        nl += key < v;
-        ne += key == v;
+    constexpr int IT = kChunk / kBlock;
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+        const int e = e0 + threadIdx.x + q * kBlock;
+        if (e < e1) {
+            const uint32_t key = keys[r.x + e];
+            nl += key < v;
+            ne += key == v;
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -262,21 +322,46 @@ __global__ __launch_bounds__(kBlock) void k_part_count(const uint32_t *__restric
     }
 }
 
-__global__ void k_part_scan(int2 *counts, int nseg, int bps) {
-    int seg = blockIdx.x * blockDim.x + threadIdx.x;
-    if (seg >= nseg) return;
+// one block per segment: exclusive scan of its blocks' (less, equal) counts
+__global__ __launch_bounds__(kBlock) void k_part_scan(int2 *__restrict__ counts, int bps) {
+    const int seg = blockIdx.x;
+    int2 *c = counts + int64_t(seg) * bps;
+    const int per = (bps + kBlock - 1) / kBlock;
+    const int i0 = threadIdx.x * per;
     int a = 0, b = 0;
-    for (int c = 0; c < bps; ++c) {
-        int2 v = counts[seg * bps + c];
-        counts[seg * bps + c] = make_int2(a, b);
-        a += v.x;
-        b += v.y;
+    for (int q = 0; q < per; ++q)
+        if (i0 + q < bps) {
+            a += c[i0 + q].x;
+            b += c[i0 + q].y;
+        }
+    __shared__ int sa[kBlock], sb[kBlock];
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const int va = threadIdx.x >= off ? sa[threadIdx.x - off] : 0;
+        const int vb = threadIdx.x >= off ? sb[threadIdx.x - off] : 0;
+        __syncthreads();
+        sa[threadIdx.x] += va;
+        sb[threadIdx.x] += vb;
+        __syncthreads();
     }
+    int ra = sa[threadIdx.x] - a, rb = sb[threadIdx.x] - b;
+    for (int q = 0; q < per; ++q)
+        if (i0 + q < bps) {
+            const int2 v = c[i0 + q];
+            c[i0 + q] = make_int2(ra, rb);
+            ra += v.x;
+            rb += v.y;
+        }
 }
 
+template <int DP>
 __global__ __launch_bounds__(kBlock) void k_part_scatter(const uint32_t *__restrict__ keys,
                                                          const int *__restrict__ idx_in,
                                                          int *__restrict__ idx_out,
+                                                         const float *__restrict__ cur,
+                                                         float *__restrict__ nxt,
                                                          const int2 *__restrict__ range,
                                                          int node0, int bps,
                                                          const Sel *__restrict__ sel,
@@ -326,29 +411,51 @@ __global__ __launch_bounds__(kBlock) void k_part_scatter(const uint32_t *__restr
                 pos = min(max(pos, 0), r.y - 1);
             }
             idx_out[r.x + pos] = idx_in[r.x + e];
+            const float4 *src = reinterpret_cast<const float4 *>(cur + int64_t(r.x + e) * DP);
+            float4 *dst = reinterpret_cast<float4 *>(nxt + int64_t(r.x + pos) * DP);
+#pragma unroll
+            for (int q = 0; q < DP / 4; ++q) dst[q] = src[q];
         }
         run_l += tl;
         run_e += te;
     }
 }
 
-// ---- one wave finishes a segment's subtree in LDS -------------------------
+// ---- one wave finishes a segment's subtree ------------------------------------
+// The segment's rows are contiguous in `cur`; for small strides they are
+// staged in LDS.  sidx holds local row numbers in the current order.  At the
+// end the rows are written in final (tree) order to `out_pts` and their
+// original indices to `out_perm`.
 template <int DP>
-__global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ P, int d,
-                                                    int *__restrict__ idx,
+__global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ cur, int d,
+                                                    const int *__restrict__ idx_glob,
                                                     const int2 *__restrict__ range, int l0,
                                                     int L, float *__restrict__ box,
                                                     int *__restrict__ split_dim,
-                                                    int *__restrict__ err) {
+                                                    int *__restrict__ err,
+                                                    float *__restrict__ out_pts,
+                                                    int *__restrict__ out_perm) {
+    constexpr bool kLds = DP <= 8;
     const int seg = blockIdx.x, lane = threadIdx.x;
     const int2 rr = range[(1 << l0) - 1 + seg];
     const int base = rr.x, c = rr.y;
     __shared__ int sidx[2][kLocalMax];
     __shared__ uint32_t skey[kLocalMax];
     __shared__ int hist[256];
-    for (int e = lane; e < c; e += 64) sidx[0][e] = idx[base + e];
+    __shared__ float spts[kLds ? kLocalMax * DP : 4];
+    const float *gpts = cur + int64_t(base) * DP;
+    if constexpr (kLds) {
+        for (int t = lane; t < c * DP; t += 64) spts[t] = gpts[t];
+    }
+    auto X = [&](int row, int j) -> float {
+        if constexpr (kLds)
+            return spts[row * DP + j];
+        else
+            return gpts[int64_t(row) * DP + j];
+    };
+    for (int e = lane; e < c; e += 64) sidx[0][e] = e;
     __syncthreads();
-    int cur = 0;
+    int cb = 0;
     const int j_l = lane % DP, grp = lane / DP;
     constexpr int NG = 64 / DP;
     for (int lv = l0; lv < L; ++lv) {
@@ -357,12 +464,12 @@ __global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ P,
             const int node = (1 << lv) - 1 + seg * nsub + sub;
             const int2 nr = range[node];
             const int o = nr.x - base, cc = nr.y;
-            const int *src = sidx[cur] + o;
+            const int *src = sidx[cb] + o;
             // box over the node's points
             uint32_t lo = 0xffffffffu, hi = 0u;
             if (j_l < d) {
                 for (int e = grp; e < cc; e += NG) {
-                    uint32_t k = f2key(P[int64_t(src[e]) * d + j_l]);
+                    uint32_t k = f2key(X(src[e], j_l));
                     lo = min(lo, k);
                     hi = max(hi, k);
                 }
@@ -395,7 +502,7 @@ __global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ P,
             const int jsplit = cand ? (__ffsll((unsigned long long)cand) - 1) : 0;
             if (lane == 0) split_dim[node] = jsplit;
             // keys
-            for (int e = lane; e < cc; e += 64) skey[o + e] = f2key(P[int64_t(src[e]) * d + jsplit]);
+            for (int e = lane; e < cc; e += 64) skey[o + e] = f2key(X(src[e], jsplit));
             __syncthreads();
             // radix select of the key at rank floor(cc/2)
             const int m = cc / 2;
@@ -451,7 +558,7 @@ __global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ P,
                 __syncthreads();
             }
             // stable partition into the other buffer
-            int *dst = sidx[cur ^ 1] + o;
+            int *dst = sidx[cb ^ 1] + o;
             int run_l = 0, run_e = 0;
             for (int b0 = 0; b0 < cc; b0 += 64) {
                 const int e = b0 + lane;
@@ -476,30 +583,14 @@ __global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ P,
             }
             __syncthreads();
         }
-        cur ^= 1;
+        cb ^= 1;
     }
-    for (int e = lane; e < c; e += 64) idx[base + e] = sidx[cur][e];
-}
-
-// ---- gather into tree order, non-finite check ------------------------------
-template <int DP>
-__global__ void k_gather(const float *__restrict__ P, int64_t n, int d, const int *__restrict__ idx,
-                         float *__restrict__ pts, int32_t *__restrict__ perm,
-                         int *__restrict__ nonfinite) {
-    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    int64_t p = t / DP;
-    int j = int(t % DP);
-    if (p >= n + kPadRows) return;
-    float v = 0.f;
-    if (p < n) {
-        int src = idx[p];
-        if (j == 0) perm[p] = src;
-        if (j < d) {
-            v = P[int64_t(src) * d + j];
-            if (!isfinite(v)) atomicOr(nonfinite, 1);
-        }
+    // final order: rows and original indices
+    for (int e = lane; e < c; e += 64) out_perm[base + e] = idx_glob[base + sidx[cb][e]];
+    for (int t = lane; t < c * DP; t += 64) {
+        const int e = t / DP, j = t % DP;
+        out_pts[int64_t(base + e) * DP + j] = X(sidx[cb][e], j);
     }
-    pts[p * DP + j] = v;
 }
 
 // leaf-blocked copy of the tree-ordered points for the BaseCase tiles
@@ -609,12 +700,13 @@ __global__ void k_internal_lambda(const int2 *__restrict__ range, int node0, int
 
 template <int DP>
 knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream_t s,
-                      knn_tree *t) {
+                      knn_tree *t, hipEvent_t done) {
     const int L = t->depth;
     const int n_nodes = int(t->n_nodes);
     const int nn = int(n);
     int *idxA = nullptr, *idxB = nullptr, *flag = nullptr, *hist = nullptr;
     uint32_t *keys = nullptr, *boxu = nullptr;
+    float *cur = nullptr, *nxt = nullptr;
     Sel *sel = nullptr;
     int2 *counts = nullptr;
     struct Guard {
@@ -624,65 +716,72 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
             for (void *q : p) free_async(q, s);
         }
     } g{s, {}};
-    KNN_HIP(alloc_async(&idxA, n, s));
-    g.p.push_back(idxA);
-    KNN_HIP(alloc_async(&idxB, n, s));
-    g.p.push_back(idxB);
-    KNN_HIP(alloc_async(&keys, n, s));
-    g.p.push_back(keys);
-    KNN_HIP(alloc_async(&flag, 1, s));
-    g.p.push_back(flag);
+    auto get = [&](auto **ptr, size_t cnt) -> hipError_t {
+        hipError_t e = alloc_async(ptr, cnt, s);
+        if (e == hipSuccess) g.p.push_back(*ptr);
+        return e;
+    };
+    const size_t rows = size_t(n) + kPadRows;
+    KNN_HIP(get(&idxA, n));
+    KNN_HIP(get(&flag, 1));
+    KNN_HIP(get(&cur, rows * DP));
     KNN_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
 
     k_ranges<<<(n_nodes + 255) / 256, 256, 0, s>>>(t->range, nn, n_nodes);
-    k_iota<<<(nn + 255) / 256, 256, 0, s>>>(idxA, nn);
+    {
+        const int64_t tot = int64_t(rows) * DP;
+        k_init<DP><<<int((tot + 255) / 256), 256, 0, s>>>(points, n, d, cur, idxA, flag);
+    }
 
-    int l = 0;
     auto cmax = [&](int lv) { return int((n + (int64_t(1) << lv) - 1) >> lv); };
-    while (l < L && cmax(l) > kLocalMax) {
+    int n_global = 0, maxseg = 1, maxblk = 1;
+    for (int q = 0; q < L && cmax(q) > kLocalMax; ++q) {
+        n_global = q + 1;
+        maxseg = std::max(maxseg, 1 << q);
+        maxblk = std::max(maxblk, (1 << q) * ((cmax(q) + kChunk - 1) / kChunk));
+    }
+    if (n_global > 0) {
+        KNN_HIP(get(&idxB, n));
+        KNN_HIP(get(&keys, n));
+        KNN_HIP(get(&nxt, rows * DP));
+        KNN_HIP(get(&boxu, size_t(maxseg) * 2 * DP));
+        KNN_HIP(get(&sel, maxseg));
+        KNN_HIP(get(&hist, size_t(maxseg) * kBins));
+        KNN_HIP(get(&counts, size_t(maxblk)));
+        KNN_HIP(hipMemsetAsync(hist, 0, size_t(maxseg) * kBins * sizeof(int), s));
+        // boxu: lo words all-ones, hi words zero
+        const int nbox = maxseg * 2 * DP;
+        k_fill_box<<<(nbox + 255) / 256, 256, 0, s>>>(boxu, nbox, DP);
+        KNN_HIP(hipMemsetAsync(nxt + size_t(n) * DP, 0, size_t(kPadRows) * DP * sizeof(float), s));
+    }
+    for (int l = 0; l < n_global; ++l) {
         const int nseg = 1 << l, node0 = nseg - 1;
         const int bps = (cmax(l) + kChunk - 1) / kChunk;
         const int nblk = nseg * bps;
-        if (!boxu) {
-            // sized for the largest grid-wide level (segments and blocks)
-            int maxseg = 1, maxblk = 1;
-            for (int q = 0; q < L && cmax(q) > kLocalMax; ++q) {
-                maxseg = std::max(maxseg, 1 << q);
-                maxblk = std::max(maxblk, (1 << q) * ((cmax(q) + kChunk - 1) / kChunk));
-            }
-            KNN_HIP(alloc_async(&boxu, size_t(maxseg) * 2 * DP, s));
-            g.p.push_back(boxu);
-            KNN_HIP(alloc_async(&sel, maxseg, s));
-            g.p.push_back(sel);
-            KNN_HIP(alloc_async(&hist, size_t(maxseg) * 256, s));
-            g.p.push_back(hist);
-            KNN_HIP(alloc_async(&counts, size_t(maxblk), s));
-            g.p.push_back(counts);
-        }
-        const int nbox = nseg * 2 * DP;
-        k_fill_u32<<<(nbox + 255) / 256, 256, 0, s>>>(boxu, nbox, 0xffffffffu, 0u, DP);
-        k_box_level<DP><<<nblk, kBlock, 0, s>>>(points, d, idxA, t->range, node0, bps, boxu);
+        k_box_level<DP><<<nblk, kBlock, 0, s>>>(cur, d, t->range, node0, bps, boxu);
         k_box_finalize<DP><<<(nseg + 63) / 64, 64, 0, s>>>(boxu, t->range, node0, nseg, d, t->box,
                                                           t->split_dim, sel);
-        KNN_HIP(hipMemsetAsync(hist, 0, size_t(nseg) * 256 * sizeof(int), s));
-        for (int pass = 0; pass < 4; ++pass) {
-            k_hist<DP><<<nblk, kBlock, 0, s>>>(points, d, idxA, t->range, node0, bps, t->split_dim,
-                                              keys, sel, hist, pass);
-            k_select<<<nseg, 64, 0, s>>>(hist, sel, t->range, node0, pass);
+        for (int pass = 0; pass < 3; ++pass) {
+            k_hist<DP><<<nblk, kBlock, 0, s>>>(cur, t->range, node0, bps, t->split_dim, keys, sel,
+                                               hist, pass);
+            k_select<<<nseg, kBlock, 0, s>>>(hist, sel, t->range, node0, pass);
         }
         k_part_count<<<nblk, kBlock, 0, s>>>(keys, t->range, node0, bps, sel, counts);
-        k_part_scan<<<(nseg + 63) / 64, 64, 0, s>>>(counts, nseg, bps);
-        k_part_scatter<<<nblk, kBlock, 0, s>>>(keys, idxA, idxB, t->range, node0, bps, sel, counts,
-                                               flag);
+        k_part_scan<<<nseg, kBlock, 0, s>>>(counts, bps);
+        k_part_scatter<DP><<<nblk, kBlock, 0, s>>>(keys, idxA, idxB, cur, nxt, t->range, node0, bps,
+                                                   sel, counts, flag);
         std::swap(idxA, idxB);
-        ++l;
+        std::swap(cur, nxt);
     }
-    if (l < L) {
-        k_local_build<DP><<<1 << l, 64, 0, s>>>(points, d, idxA, t->range, l, L, t->box,
-                                               t->split_dim, flag);
+    if (n_global < L) {
+        KNN_HIP(hipMemsetAsync(t->pts + size_t(n) * DP, 0, size_t(kPadRows) * DP * sizeof(float), s));
+        k_local_build<DP><<<1 << n_global, 64, 0, s>>>(cur, d, idxA, t->range, n_global, L, t->box,
+                                                       t->split_dim, flag, t->pts, t->perm);
+    } else {
+        // no split below the root (n <= leaf size): tree order = input order
+        KNN_HIP(hipMemcpyAsync(t->pts, cur, rows * DP * sizeof(float), hipMemcpyDeviceToDevice, s));
+        KNN_HIP(hipMemcpyAsync(t->perm, idxA, size_t(n) * sizeof(int), hipMemcpyDeviceToDevice, s));
     }
-    const int64_t tot = (n + kPadRows) * DP;
-    k_gather<DP><<<int((tot + 255) / 256), 256, 0, s>>>(points, n, d, idxA, t->pts, t->perm, flag);
     k_leaf_stats<DP><<<int(t->n_leaves), 64, 0, s>>>(t->pts, t->range, int(t->first_leaf),
                                                      int(t->n_leaves), d, t->box, t->lam,
                                                      t->split_dim);
@@ -698,6 +797,7 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
                                                             t->lam);
     }
     KNN_HIP(hipGetLastError());
+    KNN_HIP(hipEventRecord(done, s));
     int hflag = 0;
     KNN_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     KNN_HIP(hipStreamSynchronize(s));
@@ -710,13 +810,17 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
 
 void free_tree(knn_tree *t) {
     if (!t) return;
-    hipFree(t->pts);
-    hipFree(t->lpts);
-    hipFree(t->perm);
-    hipFree(t->range);
-    hipFree(t->box);
-    hipFree(t->lam);
-    hipFree(t->split_dim);
+    int cur = 0;
+    const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != t->device;
+    if (switch_dev) (void)hipSetDevice(t->device);
+    free_async(t->pts, t->stream);
+    free_async(t->lpts, t->stream);
+    free_async(t->perm, t->stream);
+    free_async(t->range, t->stream);
+    free_async(t->box, t->stream);
+    free_async(t->lam, t->stream);
+    free_async(t->split_dim, t->stream);
+    if (switch_dev) (void)hipSetDevice(cur);
     delete t;
 }
 
@@ -736,19 +840,20 @@ knn_status build_tree(const float *points, int64_t n, int d, int leaf, hipStream
         t->leaf_slots = int32_t((max_leaf + 7) / 8 * 8);
     }
     KNN_HIP(hipGetDevice(&t->device));
+    t->stream = s;
     const int dp = t->dp;
     auto cleanup_fail = [&](knn_status st) {
         free_tree(t);
         return st;
     };
     hipError_t e = hipSuccess;
-    e = e ? e : hipMalloc(&t->pts, size_t(n + kPadRows) * dp * sizeof(float));
-    e = e ? e : hipMalloc(&t->lpts, size_t(t->n_leaves) * t->leaf_slots * dp * sizeof(float));
-    e = e ? e : hipMalloc(&t->perm, size_t(n) * sizeof(int32_t));
-    e = e ? e : hipMalloc(&t->range, size_t(t->n_nodes) * sizeof(int2));
-    e = e ? e : hipMalloc(&t->box, size_t(t->n_nodes) * 2 * dp * sizeof(float));
-    e = e ? e : hipMalloc(&t->lam, size_t(t->n_nodes) * sizeof(float));
-    e = e ? e : hipMalloc(&t->split_dim, size_t(t->n_nodes) * sizeof(int32_t));
+    e = e ? e : alloc_async(&t->pts, size_t(n + kPadRows) * dp, s);
+    e = e ? e : alloc_async(&t->lpts, size_t(t->n_leaves) * t->leaf_slots * dp, s);
+    e = e ? e : alloc_async(&t->perm, size_t(n), s);
+    e = e ? e : alloc_async(&t->range, size_t(t->n_nodes), s);
+    e = e ? e : alloc_async(&t->box, size_t(t->n_nodes) * 2 * dp, s);
+    e = e ? e : alloc_async(&t->lam, size_t(t->n_nodes), s);
+    e = e ? e : alloc_async(&t->split_dim, size_t(t->n_nodes), s);
     if (e != hipSuccess) {
         cleanup_fail(KNN_OK);
         return fail(e == hipErrorOutOfMemory ? KNN_E_OOM : KNN_E_DEVICE,
@@ -760,17 +865,13 @@ knn_status build_tree(const float *points, int64_t n, int d, int leaf, hipStream
     KNN_HIP(hipEventRecord(ev0, s));
     knn_status st;
     switch (dp) {
-        case 4: st = build_impl<4>(points, n, d, leaf, s, t); break;
-        case 8: st = build_impl<8>(points, n, d, leaf, s, t); break;
-        case 16: st = build_impl<16>(points, n, d, leaf, s, t); break;
-        case 32: st = build_impl<32>(points, n, d, leaf, s, t); break;
-        default: st = build_impl<64>(points, n, d, leaf, s, t); break;
+        case 4: st = build_impl<4>(points, n, d, leaf, s, t, ev1); break;
+        case 8: st = build_impl<8>(points, n, d, leaf, s, t, ev1); break;
+        case 16: st = build_impl<16>(points, n, d, leaf, s, t, ev1); break;
+        case 32: st = build_impl<32>(points, n, d, leaf, s, t, ev1); break;
+        default: st = build_impl<64>(points, n, d, leaf, s, t, ev1); break;
     }
-    if (st == KNN_OK) {
-        (void)hipEventRecord(ev1, s);
-        (void)hipEventSynchronize(ev1);
-        (void)hipEventElapsedTime(&t->ms_build, ev0, ev1);
-    }
+    if (st == KNN_OK) (void)hipEventElapsedTime(&t->ms_build, ev0, ev1);
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
     if (st != KNN_OK) return cleanup_fail(st);

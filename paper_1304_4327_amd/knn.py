@@ -72,6 +72,8 @@ _SIGS = {
     "knn_opts_default": (None, [ctypes.POINTER(knn_opts)]),
     "knn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "knn_last_error": (ctypes.c_char_p, []),
+    "knn_release_cached_memory": (ctypes.c_int, []),
+    "knn_cached_bytes": (ctypes.c_int64, []),
     "knn_build_tree": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P,
                                       ctypes.POINTER(_P)]),
     "knn_free_tree": (None, [_P]),
@@ -176,6 +178,15 @@ def knn_build_tree(points, leaf_size: int, stream=None) -> Tree:
                                  points.shape[1], int(leaf_size), _stream(stream),
                                  ctypes.byref(out)))
     return Tree(out, points.shape[0], points.shape[1])
+
+
+def knn_release_cached_memory() -> None:
+    """Return the library's cached device blocks to the runtime."""
+    _check(load().knn_release_cached_memory())
+
+
+def knn_cached_bytes() -> int:
+    return int(load().knn_cached_bytes())
 
 
 def knn_tree_get_info(tree: Tree) -> dict:

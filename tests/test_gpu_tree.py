@@ -78,3 +78,29 @@ def test_tree_nonfinite_rejected():
     with pytest.raises(knn.KnnError) as e:
         knn.knn_build_tree(torch.from_numpy(pts).cuda(), 8)
     assert e.value.status == knn.KNN_E_NONFINITE
+
+
+def test_cached_blocks_reused_across_streams():
+    """Trees released on one stream and rebuilt on another (the caching
+    allocator hands the same blocks to the new stream after its release
+    event) still match the oracle; releasing the cache leaves live trees
+    intact."""
+    import torch
+    from paper_1304_4327_amd import knn
+    pts = datagen.uniform(20000, 3, seed=7)
+    o = okd.build(pts, 8)
+    P = torch.from_numpy(pts).cuda()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for it in range(3):
+        s = s1 if it % 2 == 0 else s2
+        with torch.cuda.stream(s):
+            t = knn.knn_build_tree(P, 8, stream=s)
+            arr = knn.tree_arrays(t)
+            t.close()
+        assert np.array_equal(arr["perm"], o["perm"])
+    assert knn.knn_cached_bytes() > 0
+    keep = knn.knn_build_tree(P, 8)
+    knn.knn_release_cached_memory()
+    assert knn.knn_cached_bytes() == 0
+    assert np.array_equal(knn.tree_arrays(keep)["perm"], o["perm"])
+    keep.close()
