@@ -55,7 +55,23 @@ def parse():
     ap.add_argument("--compare", action="store_true",
                     help="also time the plain FP32 path on the same workload and report "
                          "the speedup of the chosen variant over it")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (reference "
+                         "kernel for scaling the HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": n * 4, "bytes_written": n * 4,
+                                           "launches": 3}}))
 
 
 def cpu_baseline(ref, q, k, self_mode, target_s):
@@ -88,6 +104,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; "
                                    "--gpus must be 1 (no multi-GPU path)"}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import numpy as np
     import torch
 

@@ -77,7 +77,6 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     constexpr float kInf = __builtin_inff();
     constexpr float kSlack = 1.0f + 0x1p-16f;            // prune slack (squared)
     constexpr float kGamma = 1.0f + (D + 6) * 0x1p-24f;  // FP32 filter slack
-    const uint64_t t_start = a.wave_log ? wall_clock64() : 0;
     const int lane = threadIdx.x & 63;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int wave = blk * 4 + (threadIdx.x >> 6);
@@ -262,6 +261,7 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         const int cnt = uniform_i(rr.y);
         const float *rp = a.rlpts + int64_t(node - a.r_first_leaf) * a.r_leaf_slots * DP;
         n_pairs += uint64_t(cnt) * uint64_t(n_valid);
+        const float bnd = bound2 * kSlack;
         for (int t0 = 0; t0 < cnt; t0 += CH) {
             float sd[CH];
 #pragma unroll
@@ -274,9 +274,19 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
                 }
                 sd[c] = acc;
             }
+            // one wave-wide test per batch: most batches hold no candidate
+            // for any lane once the lists have filled
+            // (invalid lanes test against -inf; a plain compare ballots
+            // straight into a lane mask)
+            const float lim0 = fminf(dist[K - 1], bnd);
+            const float thr0 = valid ? (RESCORE ? lim0 * kGamma : lim0) : -kInf;
+            uint64_t any = 0;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) any |= ballot(sd[c] < thr0);
+            if (any == 0) continue;
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
-                const float lim = fminf(dist[K - 1], bound2 * kSlack);
+                const float lim = fminf(dist[K - 1], bnd);
                 const float thr = RESCORE ? lim * kGamma : lim;
                 const bool cand = valid && sd[c] < thr;
                 if (ballot(cand)) {
@@ -400,7 +410,8 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         for (int off = 32; off > 0; off >>= 1) ins += __shfl_xor(ins, off);
         if (a.wave_log && lane == 0) {
             uint32_t *w = a.wave_log + int64_t(wave) * 8;
-            w[0] = uint32_t(wall_clock64() - t_start);
+            w[0] = 0;  // no clock read: a side-effecting read here would
+                       // turn every uniform load above into a vector load
             w[1] = n_score;
             w[2] = n_tiles;
             w[3] = uint32_t(ins);
