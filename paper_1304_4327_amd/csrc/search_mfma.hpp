@@ -1,4 +1,5 @@
-// BF16 matrix-core traversal kernel: the same pruning dual-tree traversal
+// BF16 matrix-core traversal kernel (strides 16 and 32; stride 64 uses the
+// sweep form in search_mfma_sweep.hpp): the same pruning dual-tree traversal
 // (Algorithm 1, k-NN Score of Algorithm 3 with the bound B(N_q)), with the
 // BaseCase distance tiles (Algorithm 2) evaluated as a centred Gram product
 // on the MFMA units and every surviving candidate re-scored in FP64.
@@ -74,7 +75,6 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
     constexpr float ub = 0x1p-8f;
     constexpr float kC1 = 1.25f * 2.0f * (2.0f * ub + ub * ub);
     constexpr float kC2 = 1.25f * (DP + 8) * 0x1p-24f;
-    const uint64_t t_start = a.wave_log ? wall_clock64() : 0;
     const int lane = threadIdx.x & 63;
     const int wslot = threadIdx.x >> 6;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -387,7 +387,7 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
         for (int off = 32; off > 0; off >>= 1) ins += __shfl_xor(ins, off);
         if (a.wave_log && lane == 0) {
             uint32_t *w = a.wave_log + int64_t(wave) * 8;
-            w[0] = uint32_t(wall_clock64() - t_start);
+            w[0] = 0;
             w[1] = n_score;
             w[2] = n_tiles;
             w[3] = uint32_t(ins);

@@ -1,8 +1,8 @@
-// Instantiation of the BF16 MFMA traversal kernel for stride 64.
-#include "search_mfma.hpp"
+// Instantiation of the BF16 MFMA kernel for stride 64 (leaf sweep form).
+#include "search_mfma_sweep.hpp"
 
 namespace knnx {
 hipError_t launch_search_mfma_dp64(const SearchArgs &a, int K, int grid, hipStream_t s) {
-    return launch_search_mfma<64>(a, K, grid, s);
+    return launch_search_mfma_sweep<64>(a, K, grid, s);
 }
 }  // namespace knnx

@@ -1,0 +1,532 @@
+// BF16 matrix-core kernel for the high-dimensional regime: the same Score,
+// BaseCase tiles, bounds and exactness argument as the per-leaf MFMA kernel
+// (k_search_mfma), with the reference tree visited as a sweep over its
+// leaves instead of a depth-first walk.
+//
+// Why a sweep.  With d = 64 and tens of thousands of reference leaves, the
+// nearest-first walk enters almost every leaf anyway, and its cost becomes
+// the chain of dependent box loads on the way down and back up.  A sweep
+// scores every reference leaf against the query leaves' current bounds --
+// still a pruning dual-tree traversal (every pair (N_q, N_r) is scored at
+// most once and pruned when d_min exceeds the bound), only in another
+// order -- and lets the next leaf's data load while the current one is
+// processed.  The order starts at the leaf that the query node's box
+// centre falls in and moves outward in tree order, which keeps near leaves
+// first.
+//
+// Mapping: one workgroup of four wavefronts owns four sibling query leaves
+// (<= 32 points each, one leaf per wave).  A reference leaf kept by any of
+// the four is staged once into LDS by all 256 threads -- centred on the
+// centre c of the query leaves' union box and rounded to BF16, its FP32 rows
+// beside it for the exact re-score, and its centred row norms -- and every
+// wave whose own leaf keeps it multiplies it against its 32 queries with
+// v_mfma_f32_32x32x16_bf16 (layout, filter margin and FP64 re-score as in
+// k_search_mfma).  After every tile the waves publish their bounds in LDS at
+// the tile barrier; the query node above the four leaves adds the B(Par)
+// term min over all its queries of D_p[k] + 2 lambda(node).
+#pragma once
+
+#include "search_mfma.hpp"
+
+namespace knnx {
+
+constexpr int kWgLeaves = 4;  // query leaves (one per wave) per workgroup
+
+// LDS layout of one workgroup
+template <int DP, int K>
+struct SweepLds {
+    static constexpr int kRowBf = DP + 8;  // bf16 per staged row (16 B pad)
+    static constexpr size_t tile_f = size_t(32) * DP * 4;
+    static constexpr size_t tile_bf = size_t(32) * kRowBf * 2;
+    static constexpr size_t q_rows = size_t(kWgLeaves) * 32 * DP * 4;
+    static constexpr size_t merge = size_t(64) * K * 8;  // one wave's half-lists
+    static constexpr size_t region = q_rows > merge ? q_rows : merge;
+    static constexpr size_t off_tile_f = 0;
+    static constexpr size_t off_tile_bf = off_tile_f + tile_f;
+    static constexpr size_t off_region = off_tile_bf + tile_bf;
+    static constexpr size_t off_cen = off_region + region;
+    static constexpr size_t off_rn = off_cen + size_t(DP) * 4;
+    static constexpr size_t off_misc = off_rn + 32 * 4;
+    static constexpr size_t bytes = off_misc + 16 * 4;
+};
+
+template <int DP, int K>
+__global__ __launch_bounds__(256) void k_search_mfma_sweep(const SearchArgs a) {
+    static_assert(DP % 16 == 0, "MFMA tiles need the stride to be a multiple of 16");
+    using L = SweepLds<DP, K>;
+    constexpr int S = DP / 16;  // k-steps of 16 dimensions
+    constexpr int E = DP / 8;   // staged floats per thread (32 rows x DP / 256)
+    constexpr float kInf = __builtin_inff();
+    constexpr float kSlack = 1.0f + 0x1p-16f;
+    constexpr float ub = 0x1p-8f;
+    constexpr float kC1 = 1.25f * 2.0f * (2.0f * ub + ub * ub);
+    constexpr float kC2 = 1.25f * (DP + 8) * 0x1p-24f;
+    __shared__ __align__(16) char smem[L::bytes];
+    float *s_tf = reinterpret_cast<float *>(smem + L::off_tile_f);
+    __bf16 *s_tb = reinterpret_cast<__bf16 *>(smem + L::off_tile_bf);
+    float *s_q = reinterpret_cast<float *>(smem + L::off_region);
+    float *s_cen = reinterpret_cast<float *>(smem + L::off_cen);
+    float *s_rn = reinterpret_cast<float *>(smem + L::off_rn);
+    float *s_misc = reinterpret_cast<float *>(smem + L::off_misc);
+    // workgroup barrier that waits for this wave's LDS traffic only: the
+    // next leaf's global loads stay in flight across it
+    auto lds_barrier = [] { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); };
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int n_list = a.q_n_leaves;
+    const int leaf0 = blk * kWgLeaves;
+    if (leaf0 >= n_list) return;  // whole workgroup
+    auto leaf_on = [&](int sl) { return sl < n_list && (!a.active || a.active[sl] != 0); };
+    bool any_leaf = false;
+#pragma unroll
+    for (int g = 0; g < kWgLeaves; ++g) any_leaf |= leaf_on(leaf0 + g);
+    if (!any_leaf) return;  // whole workgroup (fallback pass)
+
+    const int slot = leaf0 + w;
+    const bool has_leaf = leaf_on(slot);
+    const int qleaf = has_leaf ? slot : leaf0;
+    const int qnode = a.q_first_leaf + qleaf;
+    const int2 qr = has_leaf ? a.qrange[qnode] : make_int2(0, 0);
+    const int qcount = uniform_i(qr.y);
+    const int j = lane & 31, h = lane >> 5;
+    const bool valid = j < qcount;
+    const int qpos = qr.x + (valid ? j : 0);
+    const int kk = a.k + (a.self ? 1 : 0);
+
+    // union box of the workgroup's active leaves, lane l = dimension l (every
+    // wave computes the same values)
+    float ulo = 0.f, uhi = 0.f;
+    if (lane < DP) {
+        ulo = kInf;
+        uhi = -kInf;
+#pragma unroll
+        for (int g = 0; g < kWgLeaves; ++g) {
+            if (leaf_on(leaf0 + g)) {
+                const float *qb = a.qbox + int64_t(a.q_first_leaf + leaf0 + g) * 2 * DP;
+                ulo = fminf(ulo, qb[lane]);
+                uhi = fmaxf(uhi, qb[DP + lane]);
+            }
+        }
+    }
+    if (w == 0 && lane < DP) s_cen[lane] = 0.5f * (ulo + uhi);
+    // each leaf's own box for Score, 64 / DP leaves per round: lane l holds
+    // dimension l % DP of leaf round * (64 / DP) + l / DP (an idle leaf's
+    // box is empty: lo = +inf, hi = -inf, so its d_min is +inf)
+    constexpr int GPR = 64 / DP;             // leaves per round
+    constexpr int ROUNDS = kWgLeaves / GPR;  // 1, 2 or 4
+    float plo[ROUNDS], phi[ROUNDS];
+#pragma unroll
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+        const int g = rd * GPR + lane / DP;
+        plo[rd] = kInf;
+        phi[rd] = -kInf;
+        if (leaf_on(leaf0 + g)) {
+            const float *qb = a.qbox + int64_t(a.q_first_leaf + leaf0 + g) * 2 * DP;
+            plo[rd] = qb[lane % DP];
+            phi[rd] = qb[DP + lane % DP];
+        }
+    }
+    // this wave's query rows (FP32) for the exact re-score; zero for idle lanes
+    float *my_q = s_q + (w * 32 + j) * DP;
+#pragma unroll
+    for (int u = h * (DP / 2); u < (h + 1) * (DP / 2); u += 4) {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (valid) v = *reinterpret_cast<const float4 *>(a.qpts + int64_t(qpos) * DP + u);
+        *reinterpret_cast<float4 *>(my_q + u) = v;
+    }
+    __syncthreads();
+
+    // query operand -2 (q - c) in BF16 and |q - c|^2 in FP32
+    bf16x8_t bq[S];
+    float qn = 0.f;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int dim = s * 16 + h * 8 + e;
+            const float qd = valid ? my_q[dim] - s_cen[dim] : 0.f;
+            qn = fmaf(qd, qd, qn);
+            bq[s][e] = (__bf16)(-2.0f * qd);
+        }
+    }
+    qn = xor32_op(qn, OpAdd());
+    const float qlen = sqrtf(qn);
+    // centre of the staged columns of this thread
+    const int trow = tid >> 3, tcol = (tid & 7) * E;
+    float tc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) tc[e] = s_cen[tcol + e];
+
+    const float lam2 = has_leaf ? 2.0f * a.qlam[qnode] : 0.f;
+    // the query node two levels above the leaves (when the tree has one)
+    float lam2_anc = kInf;
+    if (a.bound == KNN_BOUND_B && ((a.q_first_leaf + 1) >> 2) >= 1)
+        lam2_anc = 2.0f * a.qlam[((a.q_first_leaf + leaf0 + 1) >> 2) - 1];
+    const float seed = (a.seed && has_leaf) ? fmaxf(a.seed[qleaf], 0.0f) : kInf;
+    const float seed2 = seed * seed;
+
+    float dist[K];
+    int idx[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        dist[t] = (t < K - kk) ? -kInf : kInf;
+        idx[t] = -1;
+    }
+    float bound2 = (a.bound == KNN_BOUND_NONE) ? kInf : seed2;  // this wave's B^2
+    float lo_k = kInf;      // min over the wave's queries of D_p[k]^2
+    float bnd[kWgLeaves];   // every leaf's pruning bound (squared), the same in all waves
+#pragma unroll
+    for (int g = 0; g < kWgLeaves; ++g) bnd[g] = kInf;
+    float pair_kth = kInf;  // min of the two half-list k-ths of this query
+    uint32_t n_score = 0, n_tiles = 0, n_ins = 0, n_pass = 0;
+    uint64_t n_pairs = 0;
+
+    // publish the waves' bounds, then every wave derives the same
+    // workgroup bound; the barrier also ends every use of the staged tile
+    auto exchange_bounds = [&]() {
+        if (lane == 0) {
+            s_misc[w] = has_leaf ? bound2 : -kInf;
+            s_misc[kWgLeaves + w] = has_leaf ? lo_k : kInf;
+        }
+        lds_barrier();
+        float lo_all = kInf;
+#pragma unroll
+        for (int g = 0; g < kWgLeaves; ++g) lo_all = fminf(lo_all, s_misc[kWgLeaves + g]);
+        float bp = kInf;
+        if (a.bound == KNN_BOUND_B && lo_all < kInf && lam2_anc < kInf) {
+            const float t = sqrtf(lo_all) + lam2_anc;
+            bp = t * t;
+        }
+        bound2 = fminf(bound2, bp);
+#pragma unroll
+        for (int g = 0; g < kWgLeaves; ++g) bnd[g] = uniform_f(fminf(s_misc[g], bp));
+    };
+
+    // d_min^2 between each leaf's box and a reference node's box; a node is
+    // kept when any leaf would keep it (its d_min within that leaf's bound)
+    auto score_node = [&](float lo, float hi, float (&dm)[kWgLeaves]) {
+#pragma unroll
+        for (int rd = 0; rd < ROUNDS; ++rd) {
+            const float gap = fmaxf(fmaxf(lo - phi[rd], plo[rd] - hi), 0.0f);
+            float sum;
+            if constexpr (DP <= 16)
+                sum = reduce16(gap * gap, OpAdd());
+            else if constexpr (DP <= 32)
+                sum = reduce32(gap * gap, OpAdd());
+            else
+                sum = reduce64(gap * gap, OpAdd());
+#pragma unroll
+            for (int gi = 0; gi < GPR; ++gi)
+                dm[rd * GPR + gi] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sum), gi * DP));
+        }
+    };
+    auto refresh_bound = [&]() {
+        pair_kth = xor32_op(dist[K - 1], OpMin());
+        if (a.bound == KNN_BOUND_NONE) return;
+        const float hi = reduce32(valid ? pair_kth : -kInf, OpMax());
+        const float lo = reduce32(valid ? pair_kth : kInf, OpMin());
+        lo_k = uniform_f(lo);
+        float b = hi;  // B1^2
+        if (a.bound == KNN_BOUND_B) {
+            const float b2 = sqrtf(lo) + lam2;
+            b = fminf(b, b2 * b2);
+        }
+        bound2 = uniform_f(fminf(fminf(b, seed2), bound2));
+    };
+
+    auto insert = [&](float x, int id) {
+#pragma unroll
+        for (int t = K - 1; t >= 0; --t) {
+            const float dj = dist[t];
+            const float dprev = (t > 0) ? dist[t - 1] : -kInf;
+            const int iprev = (t > 0) ? idx[t - 1] : -1;
+            const bool cprev = x < dprev;
+            const bool cj = x < dj;
+            dist[t] = cprev ? dprev : (cj ? x : dj);
+            idx[t] = cprev ? iprev : (cj ? id : idx[t]);
+        }
+    };
+
+    // one tile from prefetched rows v (this thread's E columns of row trow);
+    // mine: this wave's own leaf keeps the node
+    auto tile = [&](int2 rr, const float (&v)[E], bool mine) {
+        const int base = uniform_i(rr.x);
+        const int cnt = uniform_i(rr.y);
+        // stage: rows past the leaf are zero with an infinite norm (never
+        // candidates)
+        {
+            const bool vrow = trow < cnt;
+            float rn = 0.f;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const float rd = vrow ? v[e] - tc[e] : 0.f;
+                rn = fmaf(rd, rd, rn);
+                s_tb[trow * L::kRowBf + tcol + e] = (__bf16)rd;
+                s_tf[trow * DP + tcol + e] = v[e];
+            }
+            rn = reduce8(rn, OpAdd());
+            if ((tid & 7) == 0) s_rn[trow] = vrow ? rn : kInf;
+            // largest norm of this wave's eight rows
+            const float rm = reduce64(vrow ? rn : 0.f, OpMax());
+            if (lane == 0) s_misc[2 * kWgLeaves + w] = rm;
+        }
+        lds_barrier();
+        // largest |r'| in the tile (hardware square root, 1 ulp, nudged up:
+        // the margin only needs an upper bound)
+        if (mine) {
+        ++n_tiles;
+        n_pairs += uint64_t(cnt) * uint64_t(qcount);
+        float rmax = 0.f;
+#pragma unroll
+        for (int g = 0; g < kWgLeaves; ++g) rmax = fmaxf(rmax, s_misc[2 * kWgLeaves + g]);
+        const float rlen = __builtin_amdgcn_sqrtf(uniform_f(rmax)) * (1.0f + 0x1p-20f);
+        f32x16_t acc;
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+            const float4 v = *reinterpret_cast<const float4 *>(&s_rn[g4 * 8 + h * 4]);
+            acc[g4 * 4 + 0] = v.x;
+            acc[g4 * 4 + 1] = v.y;
+            acc[g4 * 4 + 2] = v.z;
+            acc[g4 * 4 + 3] = v.w;
+        }
+        const __bf16 *arow = s_tb + j * L::kRowBf + h * 8;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const bf16x8_t ar = *reinterpret_cast<const bf16x8_t *>(arow + s * 16);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, bq[s], acc, 0, 0, 0);
+        }
+        // keep D <= T - |q'|^2 + M
+        const float lim = fminf(pair_kth, bound2) * kSlack;
+        const float marg = kC1 * qlen * rlen + kC2 * (qlen + rlen) * (qlen + rlen);
+        const float thr = valid ? lim - qn + marg : -kInf;
+        // rows past the leaf never count: their +inf would pass a +inf
+        // threshold (empty lists)
+        uint32_t mask = 0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            mask |= (acc[r] <= thr && 8 * (r >> 2) + 4 * h + (r & 3) < cnt) ? (1u << r) : 0u;
+        // survivors: one per lane per round, exact FP64 re-score, insert.
+        // The round body has no divergent branch: a lane without a survivor
+        // re-scores row 0 and inserts +inf (a no-op); the wave issues the
+        // same instructions either way.
+        for (;;) {
+            const bool has = mask != 0;
+            if (!ballot(has)) break;
+            ++n_pass;
+            const int r = has ? __builtin_ctz(mask) : 0;
+            mask &= mask - 1u;
+            const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+            const float x0 = (float)d2_fp64_rows<DP>(my_q, s_tf + row * DP);
+            const float x = has ? x0 : kInf;
+            n_ins += (x < dist[K - 1]) ? 1u : 0u;
+            insert(x, base + row);
+        }
+        refresh_bound();
+        }
+        exchange_bounds();
+    };
+
+    exchange_bounds();
+
+    // ---- sweep: the reference leaves in tree order, outward from the leaf
+    // the union centre falls in (neighbours in tree order are neighbours in
+    // space, so near leaves come first); each leaf is scored against every
+    // query leaf's bound and pruned or processed.  The next leaf's box, range
+    // and rows are loaded while the current one is processed. -------------
+    int start = 0;
+    {
+        const float cq = lane < DP ? 0.5f * (ulo + uhi) : 0.f;
+        int node = 0;
+        while (node < a.r_first_leaf) {
+            const int c0 = 2 * node + 1;
+            const float *b0 = a.rbox + int64_t(c0) * 2 * DP;
+            const float *b1 = b0 + 2 * DP;
+            const float g0 = lane < DP ? fmaxf(fmaxf(b0[lane] - cq, cq - b0[DP + lane]), 0.f) : 0.f;
+            const float g1 = lane < DP ? fmaxf(fmaxf(b1[lane] - cq, cq - b1[DP + lane]), 0.f) : 0.f;
+            const float d0 = uniform_f(reduce64(g0 * g0, OpAdd()));
+            const float d1 = uniform_f(reduce64(g1 * g1, OpAdd()));
+            node = uniform_i(d1 < d0 ? c0 + 1 : c0);
+        }
+        start = node - a.r_first_leaf;
+    }
+    const int nl = a.r_first_leaf + 1;  // reference leaves
+    const int steps = 2 * max(start, nl - 1 - start) + 1;
+    auto leaf_of = [&](int st) {
+        const int off = (st + 1) >> 1;
+        return (st & 1) ? start + off : start - off;
+    };
+    auto advance = [&](int st) {
+        while (st < steps) {
+            const int l = leaf_of(st);
+            if (l >= 0 && l < nl) break;
+            ++st;
+        }
+        return st;
+    };
+    // loads of one leaf: range, this lane's box coordinates, this thread's
+    // rows (the leaf-blocked copy has r_leaf_slots <= 32 rows per leaf)
+    auto fetch = [&](int leaf, int2 &rr, float &blo, float &bhi, float (&v)[E]) {
+        const int node = a.r_first_leaf + leaf;
+        rr = a.rrange[node];
+        const float *b = a.rbox + int64_t(node) * 2 * DP;
+        blo = b[lane % DP];
+        bhi = b[DP + lane % DP];
+        const float *rp = a.rlpts + int64_t(leaf) * a.r_leaf_slots * DP;
+        const bool in = trow < a.r_leaf_slots;
+#pragma unroll
+        for (int e = 0; e < E; e += 2) {
+            float2 x = make_float2(0.f, 0.f);
+            if (in) x = *reinterpret_cast<const float2 *>(rp + trow * DP + tcol + e);
+            v[e] = x.x;
+            v[e + 1] = x.y;
+        }
+    };
+    // score a fetched leaf and process it when any query leaf keeps it
+    auto visit = [&](int2 rr, float blo, float bhi, const float (&v)[E]) {
+        float dm[kWgLeaves];
+        score_node(blo, bhi, dm);
+        ++n_score;
+        bool keep = false;
+        float own = dm[0];
+#pragma unroll
+        for (int g = 0; g < kWgLeaves; ++g) {
+            keep |= !(dm[g] > bnd[g] * kSlack);
+            own = (w == g) ? dm[g] : own;
+        }
+        if (keep) tile(rr, v, has_leaf && !(own > bound2 * kSlack));
+    };
+    // two register sets used in turn: a leaf's loads land in the set that
+    // the next visit reads, so they stay in flight while the current leaf
+    // is processed (no register copy forces an early wait)
+    {
+        int2 rr_a = make_int2(0, 0), rr_b = make_int2(0, 0);
+        float blo_a = 0.f, bhi_a = 0.f, blo_b = 0.f, bhi_b = 0.f, v_a[E], v_b[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) v_a[e] = v_b[e] = 0.f;
+        int sc = advance(0);
+        if (sc < steps) fetch(leaf_of(sc), rr_a, blo_a, bhi_a, v_a);
+        while (sc < steps) {
+            int sn = advance(sc + 1);
+            if (sn < steps) fetch(leaf_of(sn), rr_b, blo_b, bhi_b, v_b);
+            visit(rr_a, blo_a, bhi_a, v_a);
+            sc = sn;
+            if (sc >= steps) break;
+            sn = advance(sc + 1);
+            if (sn < steps) fetch(leaf_of(sn), rr_a, blo_a, bhi_a, v_a);
+            visit(rr_b, blo_b, bhi_b, v_b);
+            sc = sn;
+        }
+    }
+
+    // ---- write-out: FP64 re-score, merge the two half-lists ------------------
+    // Every entry becomes its output key: the FP32 distance from the FP64
+    // re-score in the high word, the original index in the low word (unused
+    // slots: +inf and distinct indices that rank after every real entry).
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const bool real = valid && idx[t] >= 0 && !(a.self && idx[t] == qpos);
+        const int p = real ? idx[t] : 0;
+        float key = kInf;
+        int o = 0x7fffffff - t - h * K;
+        if (real) {
+            key = (float)sqrt(d2_fp64_rows<DP>(my_q, a.rpts + int64_t(p) * DP));
+            o = a.rperm[p];
+        }
+        dist[t] = key;
+        idx[t] = o;
+    }
+    __syncthreads();  // the query rows are no longer read: the region holds the keys
+    uint64_t *s_keys = reinterpret_cast<uint64_t *>(smem + L::off_region);
+    float worst = -1.0f;
+    for (int ww = 0; ww < kWgLeaves; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int t = 0; t < K; ++t)
+                s_keys[lane * K + t] = (uint64_t(__float_as_uint(dist[t])) << 32) | uint32_t(idx[t]);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (valid) {
+                const uint64_t *mine = s_keys + lane * K;
+                const uint64_t *other = s_keys + (lane ^ 32) * K;
+                const int64_t row = int64_t(a.qperm[qpos]) * a.k;
+#pragma unroll
+                for (int t = 0; t < K; ++t) {
+                    const uint64_t key = (uint64_t(__float_as_uint(dist[t])) << 32) | uint32_t(idx[t]);
+                    int rank = 0;
+                    for (int u = 0; u < K; ++u) rank += int(mine[u] < key) + int(other[u] < key);
+                    if (rank < a.k) {
+                        a.out_idx[row + rank] = idx[t] >= 0x7fffffff - 2 * K ? -1 : idx[t];
+                        a.out_dist[row + rank] = dist[t];
+                        if (rank == a.k - 1) worst = dist[t];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    worst = xor32_op(worst, OpMax());
+    bool fb = false;
+    if (a.seed && valid) fb = !((double)worst * worst <= (double)seed2 * (1.0 - 0x1p-20));
+    const float lw = reduce32(worst, OpMax());
+    const uint64_t fbmask = ballot(fb);
+    const float fbb = reduce32((valid && worst < kInf) ? worst : kInf, OpMin());
+    if (lane == 0 && has_leaf) {
+        if (a.leaf_kth) a.leaf_kth[qleaf] = fmaxf(lw, 0.0f);
+        if (a.fallback && fbmask) {
+            a.fallback[qleaf] = 1;
+            if (a.fb_bound) a.fb_bound[qleaf] = fbb < kInf ? (fbb + lam2) * (1.0f + 0x1p-20f) : kInf;
+        }
+    }
+    if ((a.wave_log || a.stats) && has_leaf) {
+        int ins = n_ins;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) ins += __shfl_xor(ins, off);
+        if (a.wave_log && lane == 0) {
+            uint32_t *wl = a.wave_log + int64_t(slot) * 8;
+            wl[0] = 0;
+            wl[1] = n_score;
+            wl[2] = n_tiles;
+            wl[3] = uint32_t(ins);
+            wl[4] = n_pass;
+            wl[5] = uint32_t(qleaf);
+        }
+        if (a.stats && lane == 0) {
+            atomicAdd(&a.stats[ST_SCORE], (unsigned long long)n_score);
+            atomicAdd(&a.stats[ST_TILES], (unsigned long long)n_tiles);
+            atomicAdd(&a.stats[ST_PAIRS], (unsigned long long)n_pairs);
+            atomicAdd(&a.stats[ST_INSERTS], (unsigned long long)ins);
+            atomicAdd(&a.stats[ST_FB_QUERIES], (unsigned long long)(__popcll(fbmask) / 2));
+        }
+    }
+}
+
+template <int DP>
+hipError_t launch_search_mfma_sweep(const SearchArgs &a, int K, int grid, hipStream_t s) {
+    switch (K) {
+#define KNN_CASE(KK)                                         \
+    case KK:                                                 \
+        k_search_mfma_sweep<DP, KK><<<grid, 256, 0, s>>>(a); \
+        break;
+        KNN_CASE(4)
+        KNN_CASE(5)
+        KNN_CASE(8)
+        KNN_CASE(10)
+        KNN_CASE(11)
+        KNN_CASE(16)
+        KNN_CASE(32)
+        KNN_CASE(50)
+        KNN_CASE(51)
+        KNN_CASE(64)
+#undef KNN_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace knnx
