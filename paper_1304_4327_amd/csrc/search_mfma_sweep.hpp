@@ -375,12 +375,13 @@ __global__ __launch_bounds__(256) void k_search_mfma_sweep(const SearchArgs a) {
         const float *b = a.rbox + int64_t(node) * 2 * DP;
         blo = b[lane % DP];
         bhi = b[DP + lane % DP];
-        const float *rp = a.rlpts + int64_t(leaf) * a.r_leaf_slots * DP;
-        const bool in = trow < a.r_leaf_slots;
+        // unconditional loads (a clamped row; rows past the leaf are masked
+        // at staging): a load under a branch makes the compiler wait for
+        // every load in flight where the paths join
+        const float *rp = a.rlpts + (int64_t(leaf) * a.r_leaf_slots + min(trow, a.r_leaf_slots - 1)) * DP;
 #pragma unroll
         for (int e = 0; e < E; e += 2) {
-            float2 x = make_float2(0.f, 0.f);
-            if (in) x = *reinterpret_cast<const float2 *>(rp + trow * DP + tcol + e);
+            const float2 x = *reinterpret_cast<const float2 *>(rp + tcol + e);
             v[e] = x.x;
             v[e + 1] = x.y;
         }
@@ -407,16 +408,19 @@ __global__ __launch_bounds__(256) void k_search_mfma_sweep(const SearchArgs a) {
         float blo_a = 0.f, bhi_a = 0.f, blo_b = 0.f, bhi_b = 0.f, v_a[E], v_b[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) v_a[e] = v_b[e] = 0.f;
+        // past the last step the fetch repeats the start leaf (in bounds,
+        // never visited): the loads stay unconditional
+        auto leaf_or_start = [&](int st) { return st < steps ? leaf_of(st) : start; };
         int sc = advance(0);
-        if (sc < steps) fetch(leaf_of(sc), rr_a, blo_a, bhi_a, v_a);
+        fetch(leaf_or_start(sc), rr_a, blo_a, bhi_a, v_a);
         while (sc < steps) {
             int sn = advance(sc + 1);
-            if (sn < steps) fetch(leaf_of(sn), rr_b, blo_b, bhi_b, v_b);
+            fetch(leaf_or_start(sn), rr_b, blo_b, bhi_b, v_b);
             visit(rr_a, blo_a, bhi_a, v_a);
             sc = sn;
             if (sc >= steps) break;
             sn = advance(sc + 1);
-            if (sn < steps) fetch(leaf_of(sn), rr_a, blo_a, bhi_a, v_a);
+            fetch(leaf_or_start(sn), rr_a, blo_a, bhi_a, v_a);
             visit(rr_b, blo_b, bhi_b, v_b);
             sc = sn;
         }
