@@ -32,9 +32,14 @@ PEAKS = {  # MI355X published dense peaks
     "hbm_gbs": 8000.0,
 }
 
-# HBM traffic of the traversal kernel measured with rocprofv3 --pmc
-# (FETCH_SIZE, WRITE_SIZE); None until measured for the current kernel.
-TRAFFIC_BYTES_PER_LAUNCH = {}
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same
+# counter reads for a plain 1 GiB device copy (--copy-calibration): FETCH_SIZE
+# x 2.000, WRITE_SIZE x 1.000.  Only workloads whose kernel is unchanged since
+# the counters were taken appear here.
+TRAFFIC_BYTES_PER_LAUNCH = {
+    ("gmm1m_d3_k10", "fp32"): int((61649.69 * 2.000 + 159805.28 * 1.000) * 1024),
+}
 
 
 def parse():
@@ -130,7 +135,8 @@ def main():
         train_seeds = list(range(40, 48)) if args.workload == "zipfgmm2m_d8_k10" else \
             [base + 100 + i for i in range(8)]
         t0 = time.perf_counter()
-        model = S.train_for_workload(args.workload, train_seeds, epochs=args.train_epochs)
+        model = S.train_for_workload(args.workload, train_seeds, epochs=args.train_epochs,
+                                     precision=args.precision)
         train_info = {"train_seeds": train_seeds, "eval_seed": base,
                       "train_s": time.perf_counter() - t0, "log_margin": model.log_margin,
                       "loss_first": model.history[0], "loss_last": model.history[-1]}
@@ -188,7 +194,7 @@ def main():
         peak = PEAKS["fp32_vector_tflops"]
         bound_kind, kname = "alu", "k_search_valu"
     achieved = pairs * flop_per_pair / (kern_ms * 1e-3) / 1e12
-    traffic = TRAFFIC_BYTES_PER_LAUNCH.get((args.workload, args.precision))
+    traffic = None if args.learned else TRAFFIC_BYTES_PER_LAUNCH.get((args.workload, args.precision))
     line = {
         "metric": "exact kNN queries/s, 1M\u00d71M d=3 k=10; learned+BF16 vs plain FP32 speedup",
         "value": value,

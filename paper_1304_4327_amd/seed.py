@@ -100,11 +100,14 @@ def radii(model: SeedModel, feats):
     return K.knn_seed_radius(model.mlp, feats, model.log_margin)
 
 
-def train_for_workload(name: str, train_seeds, scale: float = 1.0, **kw) -> SeedModel:
+def train_for_workload(name: str, train_seeds, scale: float = 1.0, precision: str = "fp32",
+                       **kw) -> SeedModel:
+    """Targets come from plain (exact) searches on the training seeds; the
+    precision only picks which exact path produces them."""
     feats, ys = [], []
     for s in train_seeds:
         ref, q, k, leaf = datagen.make(name, seed=s, scale=scale)
-        f, y, _ = leaf_data(ref, q, k, leaf)
+        f, y, _ = leaf_data(ref, q, k, leaf, precision=precision)
         feats.append(f)
         ys.append(y)
     return fit(feats, ys, **kw)
