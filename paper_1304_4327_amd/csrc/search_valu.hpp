@@ -51,47 +51,6 @@ __device__ inline int xcd_remap(int b, int nblk) {
     return x * q + min(x, r) + i;
 }
 
-// Cross-lane reductions: DPP row permutations within 16 lanes (no LDS
-// crossbar), shuffles across rows.  Each helper returns, in
-// every lane, op over the lane group; for a commutative op all lanes of the
-// group hold the identical value.
-template <int CTRL>
-__device__ inline float dpp_f(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                 CTRL, 0xF, 0xF, false));
-}
-// op of the lane's value and that of lane ^ 32 (or ^ 16): crossing rows of
-// 16 lanes goes through the LDS crossbar (the gfx950 row-swap builtins are
-// not used: this compiler treats both of their results as the same value)
-template <class Op>
-__device__ inline float xor32_op(float v, Op op) { return op(v, __shfl_xor(v, 32)); }
-template <class Op>
-__device__ inline float xor16_op(float v, Op op) { return op(v, __shfl_xor(v, 16)); }
-template <class Op>
-__device__ inline float reduce8(float v, Op op) {
-    v = op(v, dpp_f<0xB1>(v));   // quad_perm [1,0,3,2]
-    v = op(v, dpp_f<0x4E>(v));   // quad_perm [2,3,0,1]
-    return op(v, dpp_f<0x141>(v));  // row_half_mirror
-}
-template <class Op>
-__device__ inline float reduce16(float v, Op op) {
-    const float r = reduce8(v, op);
-    return op(r, dpp_f<0x140>(r));  // row_mirror
-}
-template <class Op>
-__device__ inline float reduce32(float v, Op op) { return xor16_op(reduce16(v, op), op); }
-template <class Op>
-__device__ inline float reduce64(float v, Op op) { return xor32_op(reduce32(v, op), op); }
-struct OpAdd {
-    __device__ float operator()(float a, float b) const { return a + b; }
-};
-struct OpMax {
-    __device__ float operator()(float a, float b) const { return fmaxf(a, b); }
-};
-struct OpMin {
-    __device__ float operator()(float a, float b) const { return fminf(a, b); }
-};
-
 __device__ inline float uniform_f(float x) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }

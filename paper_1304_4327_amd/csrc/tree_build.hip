@@ -36,8 +36,9 @@ constexpr int kChunk = 1024;     // elements per block in grid-wide levels
 constexpr int kBlock = 256;
 
 struct Sel {
-    uint32_t prefix, mask;
-    int32_t rank, pad;
+    uint32_t prefix, mask;  // key bits fixed so far
+    int32_t rank;           // rank still wanted among keys matching the prefix
+    int32_t bits;           // low bits not yet fixed (0: the median key is known)
 };
 
 __device__ inline uint64_t lanemask_lt() {
@@ -154,16 +155,20 @@ __global__ void k_box_finalize(uint32_t *__restrict__ boxu, const int2 *__restri
     float *b = box + int64_t(node) * 2 * DP;
     int best = 0;
     float bestext = -1.0f;
+    uint32_t klo = 0u, khi = 0u;  // keys of the split dimension's extremes
     for (int j = 0; j < DP; ++j) {
         float lo = 0.f, hi = 0.f;
         if (j < d) {
             if (r.y > 0) {
-                lo = key2f(boxu[(seg * 2) * DP + j]);
-                hi = key2f(boxu[(seg * 2 + 1) * DP + j]);
+                const uint32_t ulo = boxu[(seg * 2) * DP + j], uhi = boxu[(seg * 2 + 1) * DP + j];
+                lo = key2f(ulo);
+                hi = key2f(uhi);
                 const float ext = hi - lo;
                 if (ext > bestext) {
                     bestext = ext;
                     best = j;
+                    klo = ulo;
+                    khi = uhi;
                 }
             } else {
                 lo = __builtin_inff();
@@ -176,13 +181,19 @@ __global__ void k_box_finalize(uint32_t *__restrict__ boxu, const int2 *__restri
         boxu[(seg * 2 + 1) * DP + j] = 0u;
     }
     split_dim[node] = best;
-    sel[seg] = Sel{0u, 0u, r.y / 2, 0};
+    // every key of the segment shares the bits above the highest bit where
+    // the extremes differ: the digit passes start below them
+    const uint32_t diff = klo ^ khi;
+    const int bits = r.y > 0 && diff ? 32 - __clz(diff) : 0;
+    const uint32_t mask = bits >= 32 ? 0u : ~((1u << bits) - 1u);
+    sel[seg] = Sel{klo & mask, mask, r.y / 2, r.y > 0 ? bits : 0};
 }
 
-// ---- grid-wide level: radix select of the median key, 3 digits of 11 bits ----
+// ---- grid-wide level: radix select of the median key, digits of up to 11
+//      bits from the highest bit not shared by the whole segment (three
+//      passes always suffice; a segment whose key is known skips the rest) ----
 constexpr int kDigitBits = 11, kBins = 1 << kDigitBits;
-__host__ __device__ constexpr int digit_shift(int pass) { return pass == 0 ? 21 : pass == 1 ? 10 : 0; }
-__host__ __device__ constexpr uint32_t digit_mask(int pass) { return pass == 2 ? 0x3ffu : 0x7ffu; }
+__device__ inline int digit_width(int bits) { return bits < kDigitBits ? bits : kDigitBits; }
 
 template <int DP>
 __global__ __launch_bounds__(kBlock) void k_hist(const float *__restrict__ cur,
@@ -196,8 +207,9 @@ __global__ __launch_bounds__(kBlock) void k_hist(const float *__restrict__ cur,
     const int2 r = range[node];
     const int e0 = chunk * kChunk, e1 = min(r.y, e0 + kChunk);
     const Sel s = sel[seg];
-    const int shift = digit_shift(pass);
-    const uint32_t dm = digit_mask(pass);
+    if (pass > 0 && s.bits == 0) return;  // median key already known (pass 0 still writes keys)
+    const int width = digit_width(s.bits), shift = s.bits - width;
+    const uint32_t dm = (1u << width) - 1u;
     __shared__ int h[kBins];
     for (int i = threadIdx.x; i < kBins; i += kBlock) h[i] = 0;
     __syncthreads();
@@ -215,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(const float *__restrict__ cur,
             const int e = e0 + threadIdx.x + q * kBlock;
             if (e < e1) {
                 keys[r.x + e] = kv[q];
-                atomicAdd(&h[kv[q] >> shift], 1);
+                if (s.bits > 0) atomicAdd(&h[(kv[q] >> shift) & dm], 1);
             }
         }
     } else {
@@ -241,8 +253,10 @@ __global__ __launch_bounds__(kBlock) void k_select(int *__restrict__ hist, Sel *
                                                    const int2 *__restrict__ range, int node0,
                                                    int pass) {
     const int seg = blockIdx.x;
-    const int shift = digit_shift(pass);
-    const uint32_t dm = digit_mask(pass);
+    const Sel s0 = sel[seg];
+    if (s0.bits == 0) return;  // nothing counted for this segment
+    const int width = digit_width(s0.bits), shift = s0.bits - width;
+    const uint32_t dm = (1u << width) - 1u;
     int *gh = hist + int64_t(seg) * kBins;
     constexpr int PER = kBins / kBlock;  // 8 bins per thread
     int c[PER], sum = 0;
@@ -262,7 +276,6 @@ __global__ __launch_bounds__(kBlock) void k_select(int *__restrict__ hist, Sel *
         __syncthreads();
     }
     const int incl = sc[threadIdx.x], excl = incl - sum;
-    const Sel s0 = sel[seg];
     if (range[node0 + seg].y > 0 && excl <= s0.rank && s0.rank < incl) {
         int rem = s0.rank - excl, bin = threadIdx.x * PER;
 #pragma unroll
@@ -276,6 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_select(int *__restrict__ hist, Sel *
         st.prefix |= uint32_t(bin) << shift;
         st.mask |= dm << shift;
         st.rank = rem;
+        st.bits = shift;
         sel[seg] = st;
     }
 }
@@ -366,7 +380,12 @@ __global__ __launch_bounds__(kBlock) void k_part_scatter(const uint32_t *__restr
                                                          int node0, int bps,
                                                          const Sel *__restrict__ sel,
                                                          const int2 *__restrict__ counts,
-                                                         int *__restrict__ err) {
+                                                         int *__restrict__ err, int d,
+                                                         uint32_t *__restrict__ boxu_next) {
+    // boxu_next != NULL (strides <= 8): also accumulate the two children's
+    // boxes (order-preserving keys) for the next level, so that level needs
+    // no box pass of its own
+    constexpr bool kBox = DP <= 8;
     const int seg = blockIdx.x / bps, chunk = blockIdx.x % bps;
     const int2 r = range[node0 + seg];
     const int e0 = chunk * kChunk, e1 = min(r.y, e0 + kChunk);
@@ -377,6 +396,14 @@ __global__ __launch_bounds__(kBlock) void k_part_scatter(const uint32_t *__restr
     const int2 off = counts[blockIdx.x];
     const int w = threadIdx.x >> 6;
     __shared__ int wl[kBlock / 64], we[kBlock / 64];
+    float blo[2][kBox ? DP : 1], bhi[2][kBox ? DP : 1];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int j = 0; j < (kBox ? DP : 1); ++j) {
+            blo[q][j] = __builtin_inff();
+            bhi[q][j] = -__builtin_inff();
+        }
     int run_l = off.x, run_e = off.y;
     for (int base = e0; base < e1; base += kBlock) {
         const int e = base + threadIdx.x;
@@ -414,10 +441,55 @@ __global__ __launch_bounds__(kBlock) void k_part_scatter(const uint32_t *__restr
             const float4 *src = reinterpret_cast<const float4 *>(cur + int64_t(r.x + e) * DP);
             float4 *dst = reinterpret_cast<float4 *>(nxt + int64_t(r.x + pos) * DP);
 #pragma unroll
-            for (int q = 0; q < DP / 4; ++q) dst[q] = src[q];
+            for (int q = 0; q < DP / 4; ++q) {
+                const float4 x = src[q];
+                dst[q] = x;
+                if constexpr (kBox) {
+                    const float xv[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int j = 4 * q + c;
+                        if (j < d) {
+                            blo[left ? 0 : 1][j] = fminf(blo[left ? 0 : 1][j], xv[c]);
+                            bhi[left ? 0 : 1][j] = fmaxf(bhi[left ? 0 : 1][j], xv[c]);
+                        }
+                    }
+                }
+            }
         }
         run_l += tl;
         run_e += te;
+    }
+    if constexpr (kBox) {
+        if (boxu_next) {
+            // wave reduction, then one atomic per wave into the block's
+            // shared copy, then one per block into the next level's boxes
+            __shared__ uint32_t sb[2][2][DP];
+            if (threadIdx.x < 4 * DP) (&sb[0][0][0])[threadIdx.x] = (threadIdx.x / DP) & 1 ? 0u : 0xffffffffu;
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int j = 0; j < DP; ++j) {
+                    if (j >= d) continue;
+                    // float min / max (-0 and +0 map to one key below)
+                    const float a = reduce64(blo[q][j], OpMin());
+                    const float b = reduce64(bhi[q][j], OpMax());
+                    if ((threadIdx.x & 63) == 0 && a <= b) {
+                        atomicMin(&sb[q][0][j], f2key(a));
+                        atomicMax(&sb[q][1][j], f2key(b));
+                    }
+                }
+            __syncthreads();
+            if (threadIdx.x < 2 * DP) {
+                const int q = threadIdx.x / DP, j = threadIdx.x % DP;
+                const int child = 2 * seg + q;
+                if (j < d) {
+                    if (sb[q][0][j] != 0xffffffffu) atomicMin(&boxu_next[(child * 2) * DP + j], sb[q][0][j]);
+                    if (sb[q][1][j] != 0u) atomicMax(&boxu_next[(child * 2 + 1) * DP + j], sb[q][1][j]);
+                }
+            }
+        }
     }
 }
 
@@ -504,12 +576,22 @@ __global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ cu
             // keys
             for (int e = lane; e < cc; e += 64) skey[o + e] = f2key(X(src[e], jsplit));
             __syncthreads();
-            // radix select of the key at rank floor(cc/2)
             const int m = cc / 2;
-            uint32_t prefix = 0u, mask = 0u;
+            int *dst = sidx[cb ^ 1] + o;
+            // radix select of the key at rank floor(cc/2), 8-bit digits from
+            // the first bit where the node's smallest and largest keys differ
+            // (the bits above are shared by every key of the node)
+            const uint32_t klo = (uint32_t)__shfl((int)lo, jsplit);
+            const uint32_t khi = (uint32_t)__shfl((int)hi, jsplit);
+            const uint32_t diff = klo ^ khi;
+            int bits = diff ? 32 - __clz(diff) : 0;  // bits still to resolve
+            uint32_t mask = bits >= 32 ? 0u : ~((1u << bits) - 1u);
+            uint32_t prefix = klo & mask;
             int rank = m;
-            for (int pass = 0; pass < 4; ++pass) {
-                const int shift = 24 - 8 * pass;
+            while (bits > 0) {
+                const int width = bits < 8 ? bits : 8;
+                const int shift = bits - width;
+                const uint32_t dmask = (1u << width) - 1u;
                 hist[lane * 4 + 0] = 0;
                 hist[lane * 4 + 1] = 0;
                 hist[lane * 4 + 2] = 0;
@@ -517,7 +599,7 @@ __global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ cu
                 __syncthreads();
                 for (int e = lane; e < cc; e += 64) {
                     uint32_t key = skey[o + e];
-                    if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1);
+                    if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & dmask], 1);
                 }
                 __syncthreads();
                 const int h0 = hist[lane * 4 + 0], h1 = hist[lane * 4 + 1];
@@ -553,12 +635,12 @@ __global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ cu
                 bin = __shfl(bin, owner);
                 rem = __shfl(rem, owner);
                 prefix |= uint32_t(bin) << shift;
-                mask |= 255u << shift;
+                mask |= dmask << shift;
                 rank = rem;
+                bits = shift;
                 __syncthreads();
             }
             // stable partition into the other buffer
-            int *dst = sidx[cb ^ 1] + o;
             int run_l = 0, run_e = 0;
             for (int b0 = 0; b0 < cc; b0 += 64) {
                 const int e = b0 + lane;
@@ -664,11 +746,8 @@ __global__ __launch_bounds__(64) void k_leaf_stats(const float *__restrict__ pts
 // ---- internal nodes: lambda <= max_c (|C - C_c| + lambda_c), and <= the
 //      distance from C to the farthest box corner ------------------------------
 template <int DP>
-__global__ void k_internal_lambda(const int2 *__restrict__ range, int node0, int nnodes, int d,
-                                  const float *__restrict__ box, float *__restrict__ lam) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nnodes) return;
-    const int node = node0 + i;
+__device__ void internal_lambda(const int2 *__restrict__ range, int node, int d,
+                                const float *__restrict__ box, float *__restrict__ lam) {
     if (range[node].y == 0) {
         lam[node] = 0.f;
         return;
@@ -696,6 +775,36 @@ __global__ void k_internal_lambda(const int2 *__restrict__ range, int node0, int
         viakids = fmax(viakids, sqrt(dc[q]) + (double)lam[ch]);
     }
     lam[node] = round_up_f(fmin(sqrt(corner), viakids));
+}
+
+// levels [L - H, L - 1]: block b finishes the subtree under node b of level
+// L - H, bottom up (2^H - 1 nodes, a barrier between levels)
+template <int DP>
+__global__ __launch_bounds__(64) void k_lambda_subtrees(const int2 *__restrict__ range, int L,
+                                                        int H, int d,
+                                                        const float *__restrict__ box,
+                                                        float *__restrict__ lam) {
+    const int b = blockIdx.x;
+    for (int t = H - 1; t >= 0; --t) {
+        const int lv = L - H + t;
+        const int cnt = 1 << t;
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x)
+            internal_lambda<DP>(range, (1 << lv) - 1 + b * cnt + i, d, box, lam);
+        __syncthreads();
+    }
+}
+
+// levels [0, top - 1] in one block, bottom up
+template <int DP>
+__global__ __launch_bounds__(1024) void k_lambda_top(const int2 *__restrict__ range, int top,
+                                                     int d, const float *__restrict__ box,
+                                                     float *__restrict__ lam) {
+    for (int lv = top - 1; lv >= 0; --lv) {
+        const int cnt = 1 << lv;
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x)
+            internal_lambda<DP>(range, (1 << lv) - 1 + i, d, box, lam);
+        __syncthreads();
+    }
 }
 
 template <int DP>
@@ -758,7 +867,9 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
         const int nseg = 1 << l, node0 = nseg - 1;
         const int bps = (cmax(l) + kChunk - 1) / kChunk;
         const int nblk = nseg * bps;
-        k_box_level<DP><<<nblk, kBlock, 0, s>>>(cur, d, t->range, node0, bps, boxu);
+        // the box pass runs at level 0, and at every level for strides > 8
+        // (for strides <= 8 the previous level's scatter accumulated it)
+        if (l == 0 || DP > 8) k_box_level<DP><<<nblk, kBlock, 0, s>>>(cur, d, t->range, node0, bps, boxu);
         k_box_finalize<DP><<<(nseg + 63) / 64, 64, 0, s>>>(boxu, t->range, node0, nseg, d, t->box,
                                                           t->split_dim, sel);
         for (int pass = 0; pass < 3; ++pass) {
@@ -769,7 +880,8 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
         k_part_count<<<nblk, kBlock, 0, s>>>(keys, t->range, node0, bps, sel, counts);
         k_part_scan<<<nseg, kBlock, 0, s>>>(counts, bps);
         k_part_scatter<DP><<<nblk, kBlock, 0, s>>>(keys, idxA, idxB, cur, nxt, t->range, node0, bps,
-                                                   sel, counts, flag);
+                                                   sel, counts, flag, d,
+                                                   (DP <= 8 && l + 1 < n_global) ? boxu : nullptr);
         std::swap(idxA, idxB);
         std::swap(cur, nxt);
     }
@@ -791,10 +903,13 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
                                                                 int(t->first_leaf), t->n_leaves,
                                                                 t->leaf_slots, t->lpts);
     }
-    for (int lv = L - 1; lv >= 0; --lv) {
-        const int cnt = 1 << lv;
-        k_internal_lambda<DP><<<(cnt + 63) / 64, 64, 0, s>>>(t->range, cnt - 1, cnt, d, t->box,
-                                                            t->lam);
+    {
+        // internal levels: subtrees of up to 6 levels per block, then the rest
+        // of the tree in one block
+        const int H = L < 6 ? L : 6;
+        if (H > 0)
+            k_lambda_subtrees<DP><<<1 << (L - H), 64, 0, s>>>(t->range, L, H, d, t->box, t->lam);
+        if (L - H > 0) k_lambda_top<DP><<<1, 1024, 0, s>>>(t->range, L - H, d, t->box, t->lam);
     }
     KNN_HIP(hipGetLastError());
     KNN_HIP(hipEventRecord(done, s));
