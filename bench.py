@@ -142,8 +142,11 @@ def main():
                       "loss_first": model.history[0], "loss_last": model.history[-1]}
 
     def step(precision, learned=False):
-        rt = knn.knn_build_tree(R, leaf, stream=stream)
-        qt = None if self_mode else knn.knn_build_tree(Q, leaf, stream=stream)
+        # the two builds overlap on the device (second stream inside the library)
+        if self_mode:
+            rt, qt = knn.knn_build_tree(R, leaf, stream=stream), None
+        else:
+            rt, qt = knn.knn_build_tree_pair(R, Q, leaf, stream=stream)
         rad = None
         if learned:
             from paper_1304_4327_amd import seed as S

@@ -139,6 +139,17 @@ typedef struct knn_tree knn_tree;
  * Errors: KNN_E_INVALID_ARG, KNN_E_NONFINITE, KNN_E_OOM, KNN_E_DEVICE. */
 knn_status knn_build_tree(const float *points, int64_t n, int32_t d, int32_t leaf_size,
                           void *stream, knn_tree **out);
+/* Builds a reference tree and a query tree (same d and leaf size) as two
+ * knn_build_tree calls would, but lets the two builds overlap on the device:
+ * the query build runs on a library-owned stream of the current device
+ * (created on first use, default priority), which first waits for the work
+ * already queued on `stream`.  On return both builds have completed and both
+ * trees belong to `stream` (knn_free_tree releases them in its order).  On
+ * any error neither tree is returned.  Domain and errors as knn_build_tree;
+ * each of the two point sets is checked. */
+knn_status knn_build_tree_pair(const float *ref_points, int64_t n_ref, const float *query_points,
+                               int64_t n_query, int32_t d, int32_t leaf_size, void *stream,
+                               knn_tree **ref_out, knn_tree **query_out);
 void knn_free_tree(knn_tree *tree);
 
 /* Read-only view of a tree's device arrays (for tests and tools).

@@ -264,18 +264,39 @@ knn_status knn_release_cached_memory(void) {
 
 int64_t knn_cached_bytes(void) { return int64_t(cached_bytes()); }
 
+static knn_status check_build_args(const char *who, const float *points, int64_t n, int32_t d,
+                                   int32_t leaf_size) {
+    const std::string w(who);
+    if (!points) return fail(KNN_E_INVALID_ARG, w + ": points is NULL");
+    if (n < 1 || n >= (int64_t(1) << 31) - 64)
+        return fail(KNN_E_INVALID_ARG, w + ": need 1 <= n < 2^31 - 64");
+    if (d < 1 || d > 64) return fail(KNN_E_INVALID_ARG, w + ": need 1 <= d <= 64");
+    if (leaf_size < 1 || leaf_size > 64)
+        return fail(KNN_E_INVALID_ARG, w + ": need 1 <= leaf_size <= 64");
+    return KNN_OK;
+}
+
 knn_status knn_build_tree(const float *points, int64_t n, int32_t d, int32_t leaf_size,
                           void *stream, knn_tree **out) {
     set_error("");
     if (!out) return fail(KNN_E_INVALID_ARG, "knn_build_tree: out is NULL");
     *out = nullptr;
-    if (!points) return fail(KNN_E_INVALID_ARG, "knn_build_tree: points is NULL");
-    if (n < 1 || n >= (int64_t(1) << 31) - 64)
-        return fail(KNN_E_INVALID_ARG, "knn_build_tree: need 1 <= n < 2^31 - 64");
-    if (d < 1 || d > 64) return fail(KNN_E_INVALID_ARG, "knn_build_tree: need 1 <= d <= 64");
-    if (leaf_size < 1 || leaf_size > 64)
-        return fail(KNN_E_INVALID_ARG, "knn_build_tree: need 1 <= leaf_size <= 64");
+    KNN_TRY(check_build_args("knn_build_tree", points, n, d, leaf_size));
     return build_tree(points, n, d, leaf_size, (hipStream_t)stream, out);
+}
+
+knn_status knn_build_tree_pair(const float *ref_points, int64_t n_ref, const float *query_points,
+                               int64_t n_query, int32_t d, int32_t leaf_size, void *stream,
+                               knn_tree **ref_out, knn_tree **query_out) {
+    set_error("");
+    if (!ref_out || !query_out)
+        return fail(KNN_E_INVALID_ARG, "knn_build_tree_pair: an output pointer is NULL");
+    *ref_out = nullptr;
+    *query_out = nullptr;
+    KNN_TRY(check_build_args("knn_build_tree_pair (reference)", ref_points, n_ref, d, leaf_size));
+    KNN_TRY(check_build_args("knn_build_tree_pair (query)", query_points, n_query, d, leaf_size));
+    return build_tree_pair(ref_points, n_ref, query_points, n_query, d, leaf_size,
+                           (hipStream_t)stream, ref_out, query_out);
 }
 
 void knn_free_tree(knn_tree *tree) { free_tree(tree); }

@@ -137,6 +137,8 @@ struct OpMin {
 // tree construction (tree_build.hip)
 knn_status build_tree(const float *points, int64_t n, int d, int leaf, hipStream_t s,
                       knn_tree **out);
+knn_status build_tree_pair(const float *pa, int64_t na, const float *pb, int64_t nb, int d,
+                           int leaf, hipStream_t s, knn_tree **out_a, knn_tree **out_b);
 void free_tree(knn_tree *t);
 
 // Device memory for trees and scratch comes from the library's caching

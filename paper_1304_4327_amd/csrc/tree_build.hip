@@ -25,6 +25,9 @@
 // lambda gets an upper bound from the children.
 #include "common.hpp"
 
+#include <mutex>
+#include <thread>
+
 #include <algorithm>
 #include <vector>
 
@@ -809,11 +812,11 @@ __global__ __launch_bounds__(1024) void k_lambda_top(const int2 *__restrict__ ra
 
 template <int DP>
 knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream_t s,
-                      knn_tree *t, hipEvent_t done) {
+                      knn_tree *t, int *flag, hipEvent_t done) {
     const int L = t->depth;
     const int n_nodes = int(t->n_nodes);
     const int nn = int(n);
-    int *idxA = nullptr, *idxB = nullptr, *flag = nullptr, *hist = nullptr;
+    int *idxA = nullptr, *idxB = nullptr, *hist = nullptr;
     uint32_t *keys = nullptr, *boxu = nullptr;
     float *cur = nullptr, *nxt = nullptr;
     Sel *sel = nullptr;
@@ -832,7 +835,6 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
     };
     const size_t rows = size_t(n) + kPadRows;
     KNN_HIP(get(&idxA, n));
-    KNN_HIP(get(&flag, 1));
     KNN_HIP(get(&cur, rows * DP));
     KNN_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
 
@@ -913,11 +915,6 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
     }
     KNN_HIP(hipGetLastError());
     KNN_HIP(hipEventRecord(done, s));
-    int hflag = 0;
-    KNN_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    KNN_HIP(hipStreamSynchronize(s));
-    if (hflag & 1) return fail(KNN_E_NONFINITE, "knn_build_tree: non-finite coordinate in input");
-    if (hflag & 2) return fail(KNN_E_DEVICE, "knn_build_tree: internal partition inconsistency");
     return KNN_OK;
 }
 
@@ -939,9 +936,30 @@ void free_tree(knn_tree *t) {
     delete t;
 }
 
-knn_status build_tree(const float *points, int64_t n, int d, int leaf, hipStream_t s,
-                      knn_tree **out) {
+namespace {
+
+// one build in flight: its tree, stream, error flag and timing events
+struct BuildJob {
+    knn_tree *t = nullptr;
+    hipStream_t s = nullptr;
+    int *flag = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+void drop_job(BuildJob &job) {
+    free_async(job.flag, job.s);
+    if (job.ev0) (void)hipEventDestroy(job.ev0);
+    if (job.ev1) (void)hipEventDestroy(job.ev1);
+    free_tree(job.t);
+    job = BuildJob{};
+}
+
+// allocations and every launch of one build on stream s; no host wait
+knn_status build_enqueue(const float *points, int64_t n, int d, int leaf, hipStream_t s,
+                         BuildJob &job) {
     knn_tree *t = new knn_tree();
+    job.t = t;
+    job.s = s;
     t->n = n;
     t->d = d;
     t->dp = pad_dim(d);
@@ -954,14 +972,9 @@ knn_status build_tree(const float *points, int64_t n, int d, int leaf, hipStream
         const int64_t max_leaf = (n + t->n_leaves - 1) / t->n_leaves;
         t->leaf_slots = int32_t((max_leaf + 7) / 8 * 8);
     }
-    KNN_HIP(hipGetDevice(&t->device));
     t->stream = s;
     const int dp = t->dp;
-    auto cleanup_fail = [&](knn_status st) {
-        free_tree(t);
-        return st;
-    };
-    hipError_t e = hipSuccess;
+    hipError_t e = hipGetDevice(&t->device);
     e = e ? e : alloc_async(&t->pts, size_t(n + kPadRows) * dp, s);
     e = e ? e : alloc_async(&t->lpts, size_t(t->n_leaves) * t->leaf_slots * dp, s);
     e = e ? e : alloc_async(&t->perm, size_t(n), s);
@@ -969,28 +982,140 @@ knn_status build_tree(const float *points, int64_t n, int d, int leaf, hipStream
     e = e ? e : alloc_async(&t->box, size_t(t->n_nodes) * 2 * dp, s);
     e = e ? e : alloc_async(&t->lam, size_t(t->n_nodes), s);
     e = e ? e : alloc_async(&t->split_dim, size_t(t->n_nodes), s);
+    e = e ? e : alloc_async(&job.flag, 1, s);
     if (e != hipSuccess) {
-        cleanup_fail(KNN_OK);
+        drop_job(job);
         return fail(e == hipErrorOutOfMemory ? KNN_E_OOM : KNN_E_DEVICE,
                     std::string("knn_build_tree: allocation failed: ") + hipGetErrorString(e));
     }
-    hipEvent_t ev0, ev1;
-    KNN_HIP(hipEventCreate(&ev0));
-    KNN_HIP(hipEventCreate(&ev1));
-    KNN_HIP(hipEventRecord(ev0, s));
+    e = hipEventCreate(&job.ev0);
+    e = e ? e : hipEventCreate(&job.ev1);
+    e = e ? e : hipMemsetAsync(job.flag, 0, sizeof(int), s);
+    e = e ? e : hipEventRecord(job.ev0, s);
+    if (e != hipSuccess) {
+        drop_job(job);
+        return hip_fail(e, "knn_build_tree: set-up", __FILE__, __LINE__);
+    }
     knn_status st;
     switch (dp) {
-        case 4: st = build_impl<4>(points, n, d, leaf, s, t, ev1); break;
-        case 8: st = build_impl<8>(points, n, d, leaf, s, t, ev1); break;
-        case 16: st = build_impl<16>(points, n, d, leaf, s, t, ev1); break;
-        case 32: st = build_impl<32>(points, n, d, leaf, s, t, ev1); break;
-        default: st = build_impl<64>(points, n, d, leaf, s, t, ev1); break;
+        case 4: st = build_impl<4>(points, n, d, leaf, s, t, job.flag, job.ev1); break;
+        case 8: st = build_impl<8>(points, n, d, leaf, s, t, job.flag, job.ev1); break;
+        case 16: st = build_impl<16>(points, n, d, leaf, s, t, job.flag, job.ev1); break;
+        case 32: st = build_impl<32>(points, n, d, leaf, s, t, job.flag, job.ev1); break;
+        default: st = build_impl<64>(points, n, d, leaf, s, t, job.flag, job.ev1); break;
     }
-    if (st == KNN_OK) (void)hipEventElapsedTime(&t->ms_build, ev0, ev1);
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
-    if (st != KNN_OK) return cleanup_fail(st);
-    *out = t;
+    if (st != KNN_OK) {
+        (void)hipStreamSynchronize(s);  // the launches already queued must end first
+        drop_job(job);
+    }
+    return st;
+}
+
+// wait for a build, check its flag; the tree is handed out or freed
+knn_status build_finish(BuildJob &job, knn_tree **out) {
+    int hflag = 0;
+    hipError_t e = hipMemcpyAsync(&hflag, job.flag, sizeof(int), hipMemcpyDeviceToHost, job.s);
+    e = e ? e : hipStreamSynchronize(job.s);
+    if (e != hipSuccess) {
+        drop_job(job);
+        return hip_fail(e, "knn_build_tree: device work", __FILE__, __LINE__);
+    }
+    if (hflag & 1) {
+        drop_job(job);
+        return fail(KNN_E_NONFINITE, "knn_build_tree: non-finite coordinate in input");
+    }
+    if (hflag & 2) {
+        drop_job(job);
+        return fail(KNN_E_DEVICE, "knn_build_tree: internal partition inconsistency");
+    }
+    (void)hipEventElapsedTime(&job.t->ms_build, job.ev0, job.ev1);
+    free_async(job.flag, job.s);
+    (void)hipEventDestroy(job.ev0);
+    (void)hipEventDestroy(job.ev1);
+    *out = job.t;
+    job = BuildJob{};
+    return KNN_OK;
+}
+
+// a second stream per device (default priority) for the pair build
+hipError_t aux_stream(hipStream_t *out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static hipStream_t streams[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev]) {
+        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    *out = streams[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+knn_status build_tree(const float *points, int64_t n, int d, int leaf, hipStream_t s,
+                      knn_tree **out) {
+    BuildJob job;
+    KNN_TRY(build_enqueue(points, n, d, leaf, s, job));
+    return build_finish(job, out);
+}
+
+knn_status build_tree_pair(const float *pa, int64_t na, const float *pb, int64_t nb, int d,
+                           int leaf, hipStream_t s, knn_tree **out_a, knn_tree **out_b) {
+    hipStream_t s2;
+    KNN_HIP(aux_stream(&s2));
+    // the second build may only start once the caller's stream has produced
+    // its inputs
+    hipEvent_t ready;
+    KNN_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ready, s);
+    e = e ? e : hipStreamWaitEvent(s2, ready, 0);
+    (void)hipEventDestroy(ready);
+    if (e != hipSuccess) return hip_fail(e, "knn_build_tree_pair: stream join", __FILE__, __LINE__);
+    // the launches of one build take about as long to issue as to run, so
+    // the second build is issued from a second host thread
+    BuildJob ja, jb;
+    int dev = 0;
+    KNN_HIP(hipGetDevice(&dev));
+    knn_status sb = KNN_OK;
+    std::string msg_b;
+    std::thread worker([&] {
+        if (hipSetDevice(dev) != hipSuccess) {
+            sb = KNN_E_DEVICE;
+            msg_b = "knn_build_tree_pair: hipSetDevice failed in the build thread";
+            return;
+        }
+        sb = build_enqueue(pb, nb, d, leaf, s2, jb);
+        if (sb != KNN_OK) msg_b = get_error();
+    });
+    const knn_status sa0 = build_enqueue(pa, na, d, leaf, s, ja);
+    const std::string msg_a0 = get_error();
+    worker.join();
+    if (sa0 != KNN_OK || sb != KNN_OK) {
+        knn_tree *tmp = nullptr;
+        if (sa0 == KNN_OK && build_finish(ja, &tmp) == KNN_OK) free_tree(tmp);
+        tmp = nullptr;
+        if (sb == KNN_OK && build_finish(jb, &tmp) == KNN_OK) free_tree(tmp);
+        return sa0 != KNN_OK ? fail(sa0, msg_a0) : fail(sb, msg_b);
+    }
+    knn_tree *ta = nullptr, *tb = nullptr;
+    const knn_status sa = build_finish(ja, &ta);
+    const std::string msg_a = get_error();
+    const knn_status sb2 = build_finish(jb, &tb);
+    if (sa != KNN_OK || sb2 != KNN_OK) {
+        if (ta) free_tree(ta);
+        if (tb) free_tree(tb);
+        return sa != KNN_OK ? fail(sa, msg_a) : sb2;
+    }
+    // both builds have completed (finish waited for each stream); the second
+    // tree belongs to the caller's stream from now on
+    tb->stream = s;
+    *out_a = ta;
+    *out_b = tb;
     return KNN_OK;
 }
 

@@ -76,6 +76,9 @@ _SIGS = {
     "knn_cached_bytes": (ctypes.c_int64, []),
     "knn_build_tree": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P,
                                       ctypes.POINTER(_P)]),
+    "knn_build_tree_pair": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int32,
+                                           ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p)]),
     "knn_free_tree": (None, [_P]),
     "knn_tree_get_info": (ctypes.c_int, [_P, ctypes.POINTER(knn_tree_info)]),
     "knn_search": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts), _P, _P, _P]),
@@ -187,6 +190,24 @@ def knn_release_cached_memory() -> None:
 
 def knn_cached_bytes() -> int:
     return int(load().knn_cached_bytes())
+
+
+def knn_build_tree_pair(ref_points, query_points, leaf_size: int, stream=None):
+    """Build the reference and the query kd-tree with overlapping builds;
+    returns (reference Tree, query Tree)."""
+    for x, nm in ((ref_points, "ref_points"), (query_points, "query_points")):
+        if not hasattr(x, "is_cuda"):
+            raise TypeError(f"{nm} must be a CUDA tensor")
+        _dev_f32(x, nm)
+    if ref_points.shape[1] != query_points.shape[1]:
+        raise ValueError("ref_points and query_points differ in d")
+    ra, qa = ctypes.c_void_p(), ctypes.c_void_p()
+    _check(load().knn_build_tree_pair(ctypes.c_void_p(ref_points.data_ptr()), ref_points.shape[0],
+                                      ctypes.c_void_p(query_points.data_ptr()),
+                                      query_points.shape[0], ref_points.shape[1], int(leaf_size),
+                                      _stream(stream), ctypes.byref(ra), ctypes.byref(qa)))
+    return (Tree(ra, ref_points.shape[0], ref_points.shape[1]),
+            Tree(qa, query_points.shape[0], query_points.shape[1]))
 
 
 def knn_tree_get_info(tree: Tree) -> dict:

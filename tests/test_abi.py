@@ -58,6 +58,21 @@ def test_build_tree_rejects_null_points():
     assert lib.knn_build_tree(None, 10, 3, 8, None, ctypes.byref(out)) == knn.KNN_E_INVALID_ARG
 
 
+@pytest.mark.parametrize("which", ["ref_null", "query_null", "query_n", "out_null"])
+def test_build_tree_pair_rejects_bad_arguments(which):
+    lib = knn.load()
+    ra, qa = ctypes.c_void_p(), ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation comes first
+    ref = None if which == "ref_null" else fake
+    qry = None if which == "query_null" else fake
+    nq = 0 if which == "query_n" else 10
+    qout = None if which == "out_null" else ctypes.byref(qa)
+    st = lib.knn_build_tree_pair(ref, 10, qry, nq, 3, 8, None, ctypes.byref(ra), qout)
+    assert st == knn.KNN_E_INVALID_ARG
+    assert lib.knn_last_error()
+    assert not ra.value and not qa.value
+
+
 def test_search_rejects_null_tree():
     lib = knn.load()
     o = knn.knn_opts()

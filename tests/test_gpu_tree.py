@@ -104,3 +104,33 @@ def test_cached_blocks_reused_across_streams():
     assert knn.knn_cached_bytes() == 0
     assert np.array_equal(knn.tree_arrays(keep)["perm"], o["perm"])
     keep.close()
+
+
+def test_tree_pair_equals_separate_builds():
+    """The overlapping pair build gives the same two trees as two calls."""
+    import torch
+    from paper_1304_4327_amd import knn
+    ref = datagen.uniform(30000, 3, seed=11)
+    qry = datagen.uniform(17000, 3, seed=12)
+    R, Q = torch.from_numpy(ref).cuda(), torch.from_numpy(qry).cuda()
+    ta, tb = knn.knn_build_tree_pair(R, Q, 16)
+    a, b = knn.tree_arrays(ta), knn.tree_arrays(tb)
+    ta.close()
+    tb.close()
+    for pts, arr in ((ref, a), (qry, b)):
+        o = okd.build(pts, 16)
+        assert np.array_equal(arr["perm"], o["perm"])
+        live = o["count"] > 0
+        assert np.array_equal(arr["lo"][live], o["lo"][live])
+        assert np.array_equal(arr["hi"][live], o["hi"][live])
+
+
+def test_tree_pair_nonfinite_rejected():
+    import torch
+    from paper_1304_4327_amd import knn
+    ref = datagen.uniform(5000, 3, seed=13)
+    qry = datagen.uniform(4000, 3, seed=14)
+    qry[123, 1] = np.inf
+    with pytest.raises(knn.KnnError) as e:
+        knn.knn_build_tree_pair(torch.from_numpy(ref).cuda(), torch.from_numpy(qry).cuda(), 8)
+    assert e.value.status == knn.KNN_E_NONFINITE
