@@ -145,131 +145,40 @@ __global__ __launch_bounds__(kBlock) void k_box_level(const float *__restrict__ 
     }
 }
 
-// per segment: write the node box, pick the split dimension, reset the
-// accumulators for the next level, start the rank search
-template <int DP>
-__global__ void k_box_finalize(uint32_t *__restrict__ boxu, const int2 *__restrict__ range,
-                               int node0, int nseg, int d, float *__restrict__ box,
-                               int *__restrict__ split_dim, Sel *__restrict__ sel) {
-    const int seg = blockIdx.x * blockDim.x + threadIdx.x;
-    if (seg >= nseg) return;
-    const int node = node0 + seg;
-    const int2 r = range[node];
-    float *b = box + int64_t(node) * 2 * DP;
-    int best = 0;
-    float bestext = -1.0f;
-    uint32_t klo = 0u, khi = 0u;  // keys of the split dimension's extremes
-    for (int j = 0; j < DP; ++j) {
-        float lo = 0.f, hi = 0.f;
-        if (j < d) {
-            if (r.y > 0) {
-                const uint32_t ulo = boxu[(seg * 2) * DP + j], uhi = boxu[(seg * 2 + 1) * DP + j];
-                lo = key2f(ulo);
-                hi = key2f(uhi);
-                const float ext = hi - lo;
-                if (ext > bestext) {
-                    bestext = ext;
-                    best = j;
-                    klo = ulo;
-                    khi = uhi;
-                }
-            } else {
-                lo = __builtin_inff();
-                hi = -__builtin_inff();
-            }
-        }
-        b[j] = lo;
-        b[DP + j] = hi;
-        boxu[(seg * 2) * DP + j] = 0xffffffffu;
-        boxu[(seg * 2 + 1) * DP + j] = 0u;
-    }
-    split_dim[node] = best;
-    // every key of the segment shares the bits above the highest bit where
-    // the extremes differ: the digit passes start below them
-    const uint32_t diff = klo ^ khi;
-    const int bits = r.y > 0 && diff ? 32 - __clz(diff) : 0;
-    const uint32_t mask = bits >= 32 ? 0u : ~((1u << bits) - 1u);
-    sel[seg] = Sel{klo & mask, mask, r.y / 2, r.y > 0 ? bits : 0};
-}
-
-// ---- grid-wide level: radix select of the median key, digits of up to 11
-//      bits from the highest bit not shared by the whole segment (three
-//      passes always suffice; a segment whose key is known skips the rest) ----
+// ---- grid-wide level: five launches ------------------------------------------
+//   A  split dimension and box of each segment from the accumulated box keys,
+//      first digit histogram (keys stored);
+//   B  selection step on digit 0, second digit histogram, box accumulators
+//      cleared;
+//   C  selection step on digit 1, third digit histogram;
+//   D  selection step on digit 2 (the median key is known), per-block counts
+//      of keys below / equal to it;
+//   E  stable partition (each block sums the counts of the blocks before it)
+//      with the children's box keys accumulated for the next level.
+// A selection step is a block-wide scan of the segment's histogram; every
+// block of the segment takes the same step, the first block stores it.
+// Digits are up to 11 bits wide, starting below the bits that the whole
+// segment shares (the bits above the highest bit where its extremes differ);
+// three digits always suffice, and a segment whose median key is known skips
+// the remaining histograms.  Histograms are cleared by the kernel after the
+// one that reads them.
 constexpr int kDigitBits = 11, kBins = 1 << kDigitBits;
 __device__ inline int digit_width(int bits) { return bits < kDigitBits ? bits : kDigitBits; }
 
-template <int DP>
-__global__ __launch_bounds__(kBlock) void k_hist(const float *__restrict__ cur,
-                                                 const int2 *__restrict__ range, int node0,
-                                                 int bps, const int *__restrict__ split_dim,
-                                                 uint32_t *__restrict__ keys,
-                                                 const Sel *__restrict__ sel,
-                                                 int *__restrict__ hist, int pass) {
-    const int seg = blockIdx.x / bps, chunk = blockIdx.x % bps;
-    const int node = node0 + seg;
-    const int2 r = range[node];
-    const int e0 = chunk * kChunk, e1 = min(r.y, e0 + kChunk);
-    const Sel s = sel[seg];
-    if (pass > 0 && s.bits == 0) return;  // median key already known (pass 0 still writes keys)
+// block-wide: the selection after one more digit (all threads return it)
+__device__ Sel select_step(const int *__restrict__ H, Sel s) {
+    __shared__ int sc[kBlock];
+    __shared__ int sbin[2];
+    if (s.bits == 0) return s;  // uniform: the same Sel in the whole block
     const int width = digit_width(s.bits), shift = s.bits - width;
     const uint32_t dm = (1u << width) - 1u;
-    __shared__ int h[kBins];
-    for (int i = threadIdx.x; i < kBins; i += kBlock) h[i] = 0;
-    __syncthreads();
-    constexpr int IT = kChunk / kBlock;
-    uint32_t kv[IT];
-    if (pass == 0) {
-        const int j = split_dim[node];
-#pragma unroll
-        for (int q = 0; q < IT; ++q) {
-            const int e = e0 + threadIdx.x + q * kBlock;
-            kv[q] = e < e1 ? f2key(cur[int64_t(r.x + e) * DP + j]) : 0u;
-        }
-#pragma unroll
-        for (int q = 0; q < IT; ++q) {
-            const int e = e0 + threadIdx.x + q * kBlock;
-            if (e < e1) {
-                keys[r.x + e] = kv[q];
-                if (s.bits > 0) atomicAdd(&h[(kv[q] >> shift) & dm], 1);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < IT; ++q) {
-            const int e = e0 + threadIdx.x + q * kBlock;
-            kv[q] = e < e1 ? keys[r.x + e] : 0u;
-        }
-#pragma unroll
-        for (int q = 0; q < IT; ++q) {
-            const int e = e0 + threadIdx.x + q * kBlock;
-            if (e < e1 && (kv[q] & s.mask) == s.prefix) atomicAdd(&h[(kv[q] >> shift) & dm], 1);
-        }
-    }
-    __syncthreads();
-    int *gh = hist + int64_t(seg) * kBins;
-    for (int i = threadIdx.x; i < kBins; i += kBlock)
-        if (h[i]) atomicAdd(&gh[i], h[i]);
-}
-
-// one block per segment: the digit holding the wanted rank; clears the bins
-__global__ __launch_bounds__(kBlock) void k_select(int *__restrict__ hist, Sel *__restrict__ sel,
-                                                   const int2 *__restrict__ range, int node0,
-                                                   int pass) {
-    const int seg = blockIdx.x;
-    const Sel s0 = sel[seg];
-    if (s0.bits == 0) return;  // nothing counted for this segment
-    const int width = digit_width(s0.bits), shift = s0.bits - width;
-    const uint32_t dm = (1u << width) - 1u;
-    int *gh = hist + int64_t(seg) * kBins;
-    constexpr int PER = kBins / kBlock;  // 8 bins per thread
+    constexpr int PER = kBins / kBlock;
     int c[PER], sum = 0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        c[q] = gh[threadIdx.x * PER + q];
-        gh[threadIdx.x * PER + q] = 0;
+        c[q] = H[threadIdx.x * PER + q];
         sum += c[q];
     }
-    __shared__ int sc[kBlock];
     sc[threadIdx.x] = sum;
     __syncthreads();
     for (int off = 1; off < kBlock; off <<= 1) {
@@ -279,8 +188,8 @@ __global__ __launch_bounds__(kBlock) void k_select(int *__restrict__ hist, Sel *
         __syncthreads();
     }
     const int incl = sc[threadIdx.x], excl = incl - sum;
-    if (range[node0 + seg].y > 0 && excl <= s0.rank && s0.rank < incl) {
-        int rem = s0.rank - excl, bin = threadIdx.x * PER;
+    if (excl <= s.rank && s.rank < incl) {
+        int rem = s.rank - excl, bin = threadIdx.x * PER;
 #pragma unroll
         for (int q = 0; q < PER - 1; ++q) {
             if (rem >= c[q] && bin == threadIdx.x * PER + q) {
@@ -288,25 +197,164 @@ __global__ __launch_bounds__(kBlock) void k_select(int *__restrict__ hist, Sel *
                 ++bin;
             }
         }
-        Sel st = s0;
-        st.prefix |= uint32_t(bin) << shift;
-        st.mask |= dm << shift;
-        st.rank = rem;
-        st.bits = shift;
-        sel[seg] = st;
+        sbin[0] = bin;
+        sbin[1] = rem;
     }
+    __syncthreads();
+    Sel r = s;
+    r.prefix |= uint32_t(sbin[0]) << shift;
+    r.mask |= dm << shift;
+    r.rank = sbin[1];
+    r.bits = shift;
+    __syncthreads();  // sc / sbin are reused by the next step
+    return r;
 }
 
-// ---- grid-wide level: stable partition -----------------------------------------
-__global__ __launch_bounds__(kBlock) void k_part_count(const uint32_t *__restrict__ keys,
-                                                       const int2 *__restrict__ range,
-                                                       int node0, int bps,
-                                                       const Sel *__restrict__ sel,
-                                                       int2 *__restrict__ counts) {
+// histogram of the current digit of the keys matching the selection prefix;
+// PASS 0 also makes and stores the keys (coordinate of the split dimension)
+template <int DP, int PASS>
+__device__ void hist_digit(const float *__restrict__ cur, int2 r, int e0, int e1, int jsplit,
+                           uint32_t *__restrict__ keys, Sel s, int *__restrict__ gh) {
+    __shared__ int h[kBins];
+    const bool count = s.bits > 0;
+    const int width = digit_width(s.bits), shift = count ? s.bits - width : 0;
+    const uint32_t dm = (1u << width) - 1u;
+    if (count)
+        for (int i = threadIdx.x; i < kBins; i += kBlock) h[i] = 0;
+    __syncthreads();
+    constexpr int IT = kChunk / kBlock;
+    uint32_t kv[IT];
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+        const int e = e0 + threadIdx.x + q * kBlock;
+        if constexpr (PASS == 0)
+            kv[q] = e < e1 ? f2key(cur[int64_t(r.x + e) * DP + jsplit]) : 0u;
+        else
+            kv[q] = (count && e < e1) ? keys[r.x + e] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+        const int e = e0 + threadIdx.x + q * kBlock;
+        if (e < e1) {
+            if constexpr (PASS == 0) keys[r.x + e] = kv[q];
+            if (count && (kv[q] & s.mask) == s.prefix) atomicAdd(&h[(kv[q] >> shift) & dm], 1);
+        }
+    }
+    __syncthreads();
+    if (count)
+        for (int i = threadIdx.x; i < kBins; i += kBlock)
+            if (h[i]) atomicAdd(&gh[i], h[i]);
+}
+
+// this block's share of a segment's histogram bins, cleared
+__device__ inline void clear_share(int *__restrict__ gh, int chunk, int bps) {
+    const int per = (kBins + bps - 1) / bps;
+    const int b0 = chunk * per, b1 = min(kBins, b0 + per);
+    for (int i = b0 + threadIdx.x; i < b1; i += kBlock) gh[i] = 0;
+}
+
+// A: split dimension, box, first selection state, digit-0 histogram
+template <int DP>
+__global__ __launch_bounds__(kBlock) void k_level_a(const float *__restrict__ cur, int d,
+                                                    const int2 *__restrict__ range, int node0,
+                                                    int bps, const uint32_t *__restrict__ boxu,
+                                                    float *__restrict__ box,
+                                                    int *__restrict__ split_dim,
+                                                    Sel *__restrict__ sel0,
+                                                    uint32_t *__restrict__ keys,
+                                                    int *__restrict__ hist0) {
+    const int seg = blockIdx.x / bps, chunk = blockIdx.x % bps;
+    const int node = node0 + seg;
+    const int2 r = range[node];
+    __shared__ uint32_t slo[DP], shi[DP];
+    __shared__ int sbest;
+    if (threadIdx.x < DP) {
+        slo[threadIdx.x] = boxu[(seg * 2) * DP + threadIdx.x];
+        shi[threadIdx.x] = boxu[(seg * 2 + 1) * DP + threadIdx.x];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // widest extent, lowest dimension on ties
+        int best = 0;
+        float bestext = -1.0f;
+        if (r.y > 0)
+            for (int j = 0; j < d; ++j) {
+                const float ext = key2f(shi[j]) - key2f(slo[j]);
+                if (ext > bestext) {
+                    bestext = ext;
+                    best = j;
+                }
+            }
+        sbest = best;
+    }
+    __syncthreads();
+    const int best = sbest;
+    const uint32_t klo = slo[best], khi = shi[best];
+    // every key of the segment shares the bits above the highest bit where
+    // the extremes differ: the digits start below them
+    const uint32_t diff = klo ^ khi;
+    const int bits = r.y > 0 && diff ? 32 - __clz(diff) : 0;
+    const uint32_t mask = bits >= 32 ? 0u : ~((1u << bits) - 1u);
+    const Sel s0 = Sel{klo & mask, mask, r.y / 2, r.y > 0 ? bits : 0};
+    if (chunk == 0) {
+        if (threadIdx.x < DP) {
+            const int j = threadIdx.x;
+            float lo = 0.f, hi = 0.f;
+            if (j < d) {
+                lo = r.y > 0 ? key2f(slo[j]) : __builtin_inff();
+                hi = r.y > 0 ? key2f(shi[j]) : -__builtin_inff();
+            }
+            box[int64_t(node) * 2 * DP + j] = lo;
+            box[int64_t(node) * 2 * DP + DP + j] = hi;
+        }
+        if (threadIdx.x == 0) {
+            split_dim[node] = best;
+            sel0[seg] = s0;
+        }
+    }
+    const int e0 = chunk * kChunk, e1 = min(r.y, e0 + kChunk);
+    hist_digit<DP, 0>(cur, r, e0, e1, best, keys, s0, hist0 + int64_t(seg) * kBins);
+}
+
+// B, C: selection step on the previous digit, next digit's histogram.
+// B also restores the box accumulators the level has read; C clears the
+// digit-0 histogram.
+template <int PASS>
+__global__ __launch_bounds__(kBlock) void k_level_bc(const int2 *__restrict__ range, int node0,
+                                                     int bps, uint32_t *__restrict__ keys,
+                                                     const Sel *__restrict__ sel_in,
+                                                     Sel *__restrict__ sel_out,
+                                                     const int *__restrict__ hist_in,
+                                                     int *__restrict__ hist_out,
+                                                     int *__restrict__ hist_clear,
+                                                     uint32_t *__restrict__ boxu_reset, int dp) {
     const int seg = blockIdx.x / bps, chunk = blockIdx.x % bps;
     const int2 r = range[node0 + seg];
+    const Sel s = select_step(hist_in + int64_t(seg) * kBins, sel_in[seg]);
+    if (chunk == 0 && threadIdx.x == 0) sel_out[seg] = s;
+    if (boxu_reset && chunk == 0 && threadIdx.x < 2 * dp)
+        boxu_reset[seg * 2 * dp + threadIdx.x] = threadIdx.x < dp ? 0xffffffffu : 0u;
+    if (hist_clear) clear_share(hist_clear + int64_t(seg) * kBins, chunk, bps);
     const int e0 = chunk * kChunk, e1 = min(r.y, e0 + kChunk);
-    const uint32_t v = sel[seg].prefix;
+    hist_digit<4, PASS>(nullptr, r, e0, e1, 0, keys, s, hist_out + int64_t(seg) * kBins);
+}
+
+// D: last selection step; counts of keys below / equal to the median key
+__global__ __launch_bounds__(kBlock) void k_level_count(const uint32_t *__restrict__ keys,
+                                                        const int2 *__restrict__ range,
+                                                        int node0, int bps,
+                                                        const Sel *__restrict__ sel_in,
+                                                        Sel *__restrict__ sel_out,
+                                                        const int *__restrict__ hist_in,
+                                                        int *__restrict__ hist_clear,
+                                                        int2 *__restrict__ counts) {
+    const int seg = blockIdx.x / bps, chunk = blockIdx.x % bps;
+    const int2 r = range[node0 + seg];
+    const Sel s = select_step(hist_in + int64_t(seg) * kBins, sel_in[seg]);
+    if (chunk == 0 && threadIdx.x == 0) sel_out[seg] = s;
+    clear_share(hist_clear + int64_t(seg) * kBins, chunk, bps);
+    const int e0 = chunk * kChunk, e1 = min(r.y, e0 + kChunk);
+    const uint32_t v = s.prefix;
     int nl = 0, ne = 0;
     constexpr int IT = kChunk / kBlock;
 #pragma unroll
@@ -339,55 +387,21 @@ __global__ __launch_bounds__(kBlock) void k_part_count(const uint32_t *__restric
     }
 }
 
-// one block per segment: exclusive scan of its blocks' (less, equal) counts
-__global__ __launch_bounds__(kBlock) void k_part_scan(int2 *__restrict__ counts, int bps) {
-    const int seg = blockIdx.x;
-    int2 *c = counts + int64_t(seg) * bps;
-    const int per = (bps + kBlock - 1) / kBlock;
-    const int i0 = threadIdx.x * per;
-    int a = 0, b = 0;
-    for (int q = 0; q < per; ++q)
-        if (i0 + q < bps) {
-            a += c[i0 + q].x;
-            b += c[i0 + q].y;
-        }
-    __shared__ int sa[kBlock], sb[kBlock];
-    sa[threadIdx.x] = a;
-    sb[threadIdx.x] = b;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        const int va = threadIdx.x >= off ? sa[threadIdx.x - off] : 0;
-        const int vb = threadIdx.x >= off ? sb[threadIdx.x - off] : 0;
-        __syncthreads();
-        sa[threadIdx.x] += va;
-        sb[threadIdx.x] += vb;
-        __syncthreads();
-    }
-    int ra = sa[threadIdx.x] - a, rb = sb[threadIdx.x] - b;
-    for (int q = 0; q < per; ++q)
-        if (i0 + q < bps) {
-            const int2 v = c[i0 + q];
-            c[i0 + q] = make_int2(ra, rb);
-            ra += v.x;
-            rb += v.y;
-        }
-}
-
+// E: stable partition; for strides <= 8 the two children's box keys are
+// accumulated for the next level (boxu_next != NULL)
 template <int DP>
-__global__ __launch_bounds__(kBlock) void k_part_scatter(const uint32_t *__restrict__ keys,
-                                                         const int *__restrict__ idx_in,
-                                                         int *__restrict__ idx_out,
-                                                         const float *__restrict__ cur,
-                                                         float *__restrict__ nxt,
-                                                         const int2 *__restrict__ range,
-                                                         int node0, int bps,
-                                                         const Sel *__restrict__ sel,
-                                                         const int2 *__restrict__ counts,
-                                                         int *__restrict__ err, int d,
-                                                         uint32_t *__restrict__ boxu_next) {
-    // boxu_next != NULL (strides <= 8): also accumulate the two children's
-    // boxes (order-preserving keys) for the next level, so that level needs
-    // no box pass of its own
+__global__ __launch_bounds__(kBlock) void k_level_scatter(const uint32_t *__restrict__ keys,
+                                                          const int *__restrict__ idx_in,
+                                                          int *__restrict__ idx_out,
+                                                          const float *__restrict__ cur,
+                                                          float *__restrict__ nxt,
+                                                          const int2 *__restrict__ range,
+                                                          int node0, int bps,
+                                                          const Sel *__restrict__ sel,
+                                                          const int2 *__restrict__ counts,
+                                                          int *__restrict__ hist_clear,
+                                                          int *__restrict__ err, int d,
+                                                          uint32_t *__restrict__ boxu_next) {
     constexpr bool kBox = DP <= 8;
     const int seg = blockIdx.x / bps, chunk = blockIdx.x % bps;
     const int2 r = range[node0 + seg];
@@ -396,9 +410,36 @@ __global__ __launch_bounds__(kBlock) void k_part_scatter(const uint32_t *__restr
     const uint32_t v = s.prefix;
     const int req = s.rank;  // equal keys that go left
     const int m = r.y / 2;
-    const int2 off = counts[blockIdx.x];
-    const int w = threadIdx.x >> 6;
+    clear_share(hist_clear + int64_t(seg) * kBins, chunk, bps);
+    // counts of the segment's blocks before this one
     __shared__ int wl[kBlock / 64], we[kBlock / 64];
+    int2 off;
+    {
+        int a = 0, b = 0;
+        for (int c = threadIdx.x; c < chunk; c += kBlock) {
+            const int2 q = counts[seg * bps + c];
+            a += q.x;
+            b += q.y;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            a += __shfl_xor(a, o);
+            b += __shfl_xor(b, o);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            wl[threadIdx.x >> 6] = a;
+            we[threadIdx.x >> 6] = b;
+        }
+        __syncthreads();
+        a = b = 0;
+        for (int q = 0; q < kBlock / 64; ++q) {
+            a += wl[q];
+            b += we[q];
+        }
+        off = make_int2(a, b);
+        __syncthreads();
+    }
+    const int w = threadIdx.x >> 6;
     float blo[2][kBox ? DP : 1], bhi[2][kBox ? DP : 1];
 #pragma unroll
     for (int q = 0; q < 2; ++q)
@@ -465,10 +506,11 @@ __global__ __launch_bounds__(kBlock) void k_part_scatter(const uint32_t *__restr
     }
     if constexpr (kBox) {
         if (boxu_next) {
-            // wave reduction, then one atomic per wave into the block's
-            // shared copy, then one per block into the next level's boxes
+            // wave reduction, one atomic per wave into the block's copy, one
+            // per block into the next level's box keys
             __shared__ uint32_t sb[2][2][DP];
-            if (threadIdx.x < 4 * DP) (&sb[0][0][0])[threadIdx.x] = (threadIdx.x / DP) & 1 ? 0u : 0xffffffffu;
+            if (threadIdx.x < 4 * DP)
+                (&sb[0][0][0])[threadIdx.x] = ((threadIdx.x / DP) & 1) ? 0u : 0xffffffffu;
             __syncthreads();
 #pragma unroll
             for (int q = 0; q < 2; ++q)
@@ -488,7 +530,8 @@ __global__ __launch_bounds__(kBlock) void k_part_scatter(const uint32_t *__restr
                 const int q = threadIdx.x / DP, j = threadIdx.x % DP;
                 const int child = 2 * seg + q;
                 if (j < d) {
-                    if (sb[q][0][j] != 0xffffffffu) atomicMin(&boxu_next[(child * 2) * DP + j], sb[q][0][j]);
+                    if (sb[q][0][j] != 0xffffffffu)
+                        atomicMin(&boxu_next[(child * 2) * DP + j], sb[q][0][j]);
                     if (sb[q][1][j] != 0u) atomicMax(&boxu_next[(child * 2 + 1) * DP + j], sb[q][1][j]);
                 }
             }
@@ -856,15 +899,17 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
         KNN_HIP(get(&keys, n));
         KNN_HIP(get(&nxt, rows * DP));
         KNN_HIP(get(&boxu, size_t(maxseg) * 2 * DP));
-        KNN_HIP(get(&sel, maxseg));
-        KNN_HIP(get(&hist, size_t(maxseg) * kBins));
+        KNN_HIP(get(&sel, 4 * size_t(maxseg)));
+        KNN_HIP(get(&hist, 3 * size_t(maxseg) * kBins));
         KNN_HIP(get(&counts, size_t(maxblk)));
-        KNN_HIP(hipMemsetAsync(hist, 0, size_t(maxseg) * kBins * sizeof(int), s));
+        KNN_HIP(hipMemsetAsync(hist, 0, 3 * size_t(maxseg) * kBins * sizeof(int), s));
         // boxu: lo words all-ones, hi words zero
         const int nbox = maxseg * 2 * DP;
         k_fill_box<<<(nbox + 255) / 256, 256, 0, s>>>(boxu, nbox, DP);
         KNN_HIP(hipMemsetAsync(nxt + size_t(n) * DP, 0, size_t(kPadRows) * DP * sizeof(float), s));
     }
+    int *H[3] = {hist, hist + size_t(maxseg) * kBins, hist + 2 * size_t(maxseg) * kBins};
+    Sel *S[4] = {sel, sel + maxseg, sel + 2 * maxseg, sel + 3 * maxseg};
     for (int l = 0; l < n_global; ++l) {
         const int nseg = 1 << l, node0 = nseg - 1;
         const int bps = (cmax(l) + kChunk - 1) / kChunk;
@@ -872,18 +917,17 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
         // the box pass runs at level 0, and at every level for strides > 8
         // (for strides <= 8 the previous level's scatter accumulated it)
         if (l == 0 || DP > 8) k_box_level<DP><<<nblk, kBlock, 0, s>>>(cur, d, t->range, node0, bps, boxu);
-        k_box_finalize<DP><<<(nseg + 63) / 64, 64, 0, s>>>(boxu, t->range, node0, nseg, d, t->box,
-                                                          t->split_dim, sel);
-        for (int pass = 0; pass < 3; ++pass) {
-            k_hist<DP><<<nblk, kBlock, 0, s>>>(cur, t->range, node0, bps, t->split_dim, keys, sel,
-                                               hist, pass);
-            k_select<<<nseg, kBlock, 0, s>>>(hist, sel, t->range, node0, pass);
-        }
-        k_part_count<<<nblk, kBlock, 0, s>>>(keys, t->range, node0, bps, sel, counts);
-        k_part_scan<<<nseg, kBlock, 0, s>>>(counts, bps);
-        k_part_scatter<DP><<<nblk, kBlock, 0, s>>>(keys, idxA, idxB, cur, nxt, t->range, node0, bps,
-                                                   sel, counts, flag, d,
-                                                   (DP <= 8 && l + 1 < n_global) ? boxu : nullptr);
+        k_level_a<DP><<<nblk, kBlock, 0, s>>>(cur, d, t->range, node0, bps, boxu, t->box, t->split_dim,
+                                             S[0], keys, H[0]);
+        k_level_bc<1><<<nblk, kBlock, 0, s>>>(t->range, node0, bps, keys, S[0], S[1], H[0], H[1],
+                                              nullptr, boxu, DP);
+        k_level_bc<2><<<nblk, kBlock, 0, s>>>(t->range, node0, bps, keys, S[1], S[2], H[1], H[2],
+                                              H[0], nullptr, DP);
+        k_level_count<<<nblk, kBlock, 0, s>>>(keys, t->range, node0, bps, S[2], S[3], H[2], H[1],
+                                              counts);
+        k_level_scatter<DP><<<nblk, kBlock, 0, s>>>(keys, idxA, idxB, cur, nxt, t->range, node0, bps,
+                                                    S[3], counts, H[2], flag, d,
+                                                    (DP <= 8 && l + 1 < n_global) ? boxu : nullptr);
         std::swap(idxA, idxB);
         std::swap(cur, nxt);
     }
