@@ -56,6 +56,48 @@ __global__ void k_count_flags(const int *__restrict__ flag, int n, int *__restri
     if (i < n && flag[i]) atomicAdd(count, 1);
 }
 
+// Launch order of the wave slots, largest leaf radius first: a wave's cost
+// grows with its leaves' radius (sparse regions have large k-th distances),
+// and starting the heavy waves first keeps them from finishing last.
+// Counting sort on 2048 buckets of the radius' float bits (exponent and
+// three mantissa bits), descending.
+constexpr int kOrderBuckets = 2048;
+__global__ void k_order_keys(const float *__restrict__ lam, int first_leaf, int n_leaves, int ng,
+                             int n_waves, int *__restrict__ bucket, int *__restrict__ count) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= n_waves) return;
+    float r = 0.f;
+    for (int g = 0; g < ng; ++g) {
+        const int leaf = w * ng + g;
+        if (leaf < n_leaves) r = fmaxf(r, lam[first_leaf + leaf]);
+    }
+    const int b = kOrderBuckets - 1 - min(kOrderBuckets - 1, int(__float_as_uint(fmaxf(r, 0.f)) >> 20));
+    bucket[w] = b;
+    atomicAdd(&count[b], 1);
+}
+__global__ __launch_bounds__(1024) void k_order_scan(int *__restrict__ count) {
+    __shared__ int sc[1024];
+    const int t = threadIdx.x;
+    const int c0 = count[2 * t], c1 = count[2 * t + 1];
+    sc[t] = c0 + c1;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = t >= off ? sc[t - off] : 0;
+        __syncthreads();
+        sc[t] += v;
+        __syncthreads();
+    }
+    const int excl = sc[t] - c0 - c1;
+    count[2 * t] = excl;  // becomes the bucket's cursor
+    count[2 * t + 1] = excl + c0;
+}
+__global__ void k_order_scatter(const int *__restrict__ bucket, int n_waves, int *__restrict__ cursor,
+                                int *__restrict__ order) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= n_waves) return;
+    order[atomicAdd(&cursor[bucket[w]], 1)] = w;
+}
+
 struct Scratch {
     hipStream_t s;
     std::vector<void *> p;
@@ -170,6 +212,19 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
         KNN_HIP(sc.get(&wlog, size_t(grid) * 4 * 8));
         KNN_HIP(hipMemsetAsync(wlog, 0, size_t(grid) * 32 * sizeof(uint32_t), s));
         a.wave_log = wlog;
+    }
+    if (!bf16 && waves > 1) {
+        int *order = nullptr, *bucket = nullptr, *count = nullptr;
+        KNN_HIP(sc.get(&order, waves));
+        KNN_HIP(sc.get(&bucket, waves));
+        KNN_HIP(sc.get(&count, kOrderBuckets));
+        KNN_HIP(hipMemsetAsync(count, 0, kOrderBuckets * sizeof(int), s));
+        const int nb = (waves + 255) / 256;
+        k_order_keys<<<nb, 256, 0, s>>>(qt->lam, int(qt->first_leaf), nq_leaves, NG, waves, bucket,
+                                        count);
+        k_order_scan<<<1, 1024, 0, s>>>(count);
+        k_order_scatter<<<nb, 256, 0, s>>>(bucket, waves, count, order);
+        a.order = order;
     }
     hipEvent_t ev[4];
     for (auto &e : ev) KNN_HIP(hipEventCreate(&e));

@@ -35,6 +35,9 @@ struct SearchArgs {
     // leaves to process: active == NULL means all; otherwise only leaves
     // with active[leaf] != 0 (the waves keep their sibling-aligned leaves)
     const int *active;
+    // launch order of the wave slots (largest leaf radius first), or NULL:
+    // wave i of the launch takes slot order[i]
+    const int *order;
     int d, k, lpl_log2;
     int bound;          // knn_bound
     int self;           // exclude reference position == query position

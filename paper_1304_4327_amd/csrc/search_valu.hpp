@@ -78,11 +78,18 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     constexpr float kSlack = 1.0f + 0x1p-16f;            // prune slack (squared)
     constexpr float kGamma = 1.0f + (D + 6) * 0x1p-24f;  // FP32 filter slack
     const int lane = threadIdx.x & 63;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int wave = blk * 4 + (threadIdx.x >> 6);
     const int lpl_log2 = a.lpl_log2;
     const int NG = 64 >> lpl_log2;
     const int n_list = a.q_n_leaves;
+    int wave;
+    if (a.order) {
+        // heavy slots first: the hardware starts workgroups in launch order
+        const int raw = blockIdx.x * 4 + (threadIdx.x >> 6);
+        if (raw * NG >= n_list) return;
+        wave = uniform_i(a.order[raw]);
+    } else {
+        wave = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    }
     if (wave * NG >= n_list) return;
     const int g = lane >> lpl_log2, li = lane & ((1 << lpl_log2) - 1);
     const int slot = wave * NG + g;
