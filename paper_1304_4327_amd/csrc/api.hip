@@ -213,7 +213,9 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
         KNN_HIP(hipMemsetAsync(wlog, 0, size_t(grid) * 32 * sizeof(uint32_t), s));
         a.wave_log = wlog;
     }
-    if (!bf16 && waves > 1) {
+    // (the stride-64 BF16 kernel sweeps reference leaves per workgroup of
+    // four query leaves and takes no order)
+    if ((!bf16 || ref->dp < 64) && waves > 1) {
         int *order = nullptr, *bucket = nullptr, *count = nullptr;
         KNN_HIP(sc.get(&order, waves));
         KNN_HIP(sc.get(&bucket, waves));

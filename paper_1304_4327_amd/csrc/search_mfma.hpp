@@ -77,9 +77,16 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
     constexpr float kC2 = 1.25f * (DP + 8) * 0x1p-24f;
     const int lane = threadIdx.x & 63;
     const int wslot = threadIdx.x >> 6;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int wave = blk * 4 + wslot;
     const int n_list = a.q_n_leaves;
+    int wave;
+    if (a.order) {
+        // heavy leaves first: the hardware starts workgroups in launch order
+        const int raw = blockIdx.x * 4 + wslot;
+        if (raw >= n_list) return;
+        wave = uniform_i(a.order[raw]);
+    } else {
+        wave = xcd_remap(blockIdx.x, gridDim.x) * 4 + wslot;
+    }
     if (wave >= n_list) return;
     if (a.active && a.active[wave] == 0) return;
     const int qleaf = uniform_i(wave);
@@ -124,7 +131,7 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
             bq[s][e] = (__bf16)(-2.0f * qd);
         }
     }
-    qn += __shfl_xor(qn, 32);
+    qn = xor32_op(qn, OpAdd());
     const float qlen = sqrtf(qn);
     // leaf box for Score: lane l holds dimension l (0 beyond d, as stored)
     const float qlo = lane < DP ? qb[lane] : 0.f;
@@ -150,23 +157,22 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
         const float lo = lane < DP ? b[lane] : 0.f;
         const float hi = lane < DP ? b[DP + lane] : 0.f;
         const float gap = fmaxf(fmaxf(lo - qhi, qlo - hi), 0.0f);
-        float sum = gap * gap;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+        float sum;
+        if constexpr (DP <= 16)
+            sum = reduce16(gap * gap, OpAdd());
+        else if constexpr (DP <= 32)
+            sum = reduce32(gap * gap, OpAdd());
+        else
+            sum = reduce64(gap * gap, OpAdd());
         return uniform_f(sum);
     };
     auto keep_of = [&](float dmin2) { return !(dmin2 > bound2 * kSlack); };
 
     auto refresh_bound = [&]() {
-        pair_kth = fminf(dist[K - 1], __shfl_xor(dist[K - 1], 32));
+        pair_kth = xor32_op(dist[K - 1], OpMin());
         if (a.bound == KNN_BOUND_NONE) return;
-        float hi = valid ? pair_kth : -kInf;
-        float lo = valid ? pair_kth : kInf;
-#pragma unroll
-        for (int off = 16; off > 0; off >>= 1) {
-            hi = fmaxf(hi, __shfl_xor(hi, off));
-            lo = fminf(lo, __shfl_xor(lo, off));
-        }
+        const float hi = reduce32(valid ? pair_kth : -kInf, OpMax());
+        const float lo = reduce32(valid ? pair_kth : kInf, OpMin());
         float b = hi;  // B1^2
         if (a.bound == KNN_BOUND_B) {
             const float b2 = sqrtf(lo) + lam2;
@@ -215,11 +221,11 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
                 ar[s][e] = (__bf16)rd;
             }
         }
-        rn += __shfl_xor(rn, 32);
-        float rmax = vr ? rn : 0.f;
-#pragma unroll
-        for (int off = 16; off > 0; off >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, off));
-        const float rlen = sqrtf(uniform_f(rmax));
+        rn = xor32_op(rn, OpAdd());
+        const float rmax = reduce32(vr ? rn : 0.f, OpMax());
+        // hardware square root (1 ulp), nudged up: the margin only needs an
+        // upper bound
+        const float rlen = __builtin_amdgcn_sqrtf(uniform_f(rmax)) * (1.0f + 0x1p-20f);
         if (h == 0) s_rn[i] = vr ? rn : kInf;
         wave_sync();
         f32x16_t acc;
