@@ -2,8 +2,11 @@
 
 One step = the whole job on inputs already resident in HBM: build the
 reference kd-tree, build the query kd-tree, run the pruning dual-tree search,
-write the (index, distance) lists.  W untimed warm-up steps, then K timed
-steps between device synchronisations.  Prints ONE JSON line.
+write the (index, distance) lists.  The plain path is one knn_all_knn call
+(builds overlapped on two streams, search, one stream synchronisation); with
+the learned seed the trees are built first, the seed network runs on them,
+then the search.  W untimed warm-up steps, then K timed steps between device
+synchronisations.  Prints ONE JSON line.
 
 Default workload: 1,000,000 reference x 1,000,000 query points, d = 3,
 32-component Gaussian mixture, k = 10, leaf size 32, FP32 path.
@@ -37,9 +40,7 @@ PEAKS = {  # MI355X published dense peaks
 # counter reads for a plain 1 GiB device copy (--copy-calibration): FETCH_SIZE
 # x 2.000, WRITE_SIZE x 1.000.  Only workloads whose kernel is unchanged since
 # the counters were taken appear here.
-TRAFFIC_BYTES_PER_LAUNCH = {
-    ("gmm1m_d3_k10", "fp32"): int((61649.69 * 2.000 + 159805.28 * 1.000) * 1024),
-}
+TRAFFIC_BYTES_PER_LAUNCH = {}
 
 
 def parse():
@@ -142,15 +143,20 @@ def main():
                       "loss_first": model.history[0], "loss_last": model.history[-1]}
 
     def step(precision, learned=False):
-        # the two builds overlap on the device (second stream inside the library)
+        if not learned:
+            # the whole path in one library call: both builds (overlapped on
+            # two streams), the search, one stream synchronisation
+            _, _, st = knn.knn_all_knn(R, None if self_mode else Q, k, leaf, bound=args.bound,
+                                       precision=precision, exclude_self=self_mode, stats=True,
+                                       out=(idx, dist), stream=stream)
+            return st
+        # learned seed: the seed features need the trees between build and search
         if self_mode:
             rt, qt = knn.knn_build_tree(R, leaf, stream=stream), None
         else:
             rt, qt = knn.knn_build_tree_pair(R, Q, leaf, stream=stream)
-        rad = None
-        if learned:
-            from paper_1304_4327_amd import seed as S
-            rad = S.radii(model, knn.knn_seed_features(rt, qt, stream=stream))
+        from paper_1304_4327_amd import seed as S
+        rad = S.radii(model, knn.knn_seed_features(rt, qt, stream=stream))
         _, _, st = knn.knn_search(rt, qt, k, bound=args.bound, precision=precision,
                                   exclude_self=self_mode, stats=True, out=(idx, dist),
                                   seed_radius=rad, stream=stream)

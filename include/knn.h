@@ -87,6 +87,8 @@ typedef struct knn_stats {
     int32_t n_query_leaves;   /* leaves of the query tree                        */
     int64_t fallback_pairs;   /* pairs evaluated by the fallback pass (included
                                  in `pairs`)                                     */
+    float ms_ref_build;       /* device time, reference-tree build (knn_all_knn
+                                 only; 0 otherwise)                              */
 } knn_stats;
 
 typedef struct knn_opts {
@@ -200,6 +202,21 @@ knn_status knn_search(const knn_tree *ref, const knn_tree *query, int32_t k,
 knn_status knn_search_points(const knn_tree *ref, const float *queries, int64_t n_q,
                              int32_t k, const knn_opts *opts, int64_t *idx_out,
                              float *dist_out, void *stream);
+
+/* The whole path in one call: builds the reference tree and (unless
+ * query_points is NULL) the query tree, the two builds overlapped as in
+ * knn_build_tree_pair, searches as knn_search, and frees both trees.  The
+ * result equals that of the separate calls; the difference is that the
+ * search is enqueued behind the builds without a host wait in between, so
+ * the stream is synchronised once, at the end, where the builds' input
+ * checks are read.  query_points == NULL: all-kNN of ref_points on itself
+ * (opts->exclude_self as in knn_search).  Argument domains and errors are
+ * those of knn_build_tree (for each point set) and knn_search; after an
+ * error the contents of idx_out and dist_out are undefined.  With
+ * opts->stats, ms_ref_build and ms_query_build report the two builds. */
+knn_status knn_all_knn(const float *ref_points, int64_t n_ref, const float *query_points,
+                       int64_t n_query, int32_t d, int32_t leaf_size, int32_t k,
+                       const knn_opts *opts, int64_t *idx_out, float *dist_out, void *stream);
 
 
 /* ------------------------------------------------------------------------

@@ -60,42 +60,48 @@ __global__ void k_count_flags(const int *__restrict__ flag, int n, int *__restri
 // grows with its leaves' radius (sparse regions have large k-th distances),
 // and starting the heavy waves first keeps them from finishing last.
 // Counting sort on 2048 buckets of the radius' float bits (exponent and
-// three mantissa bits), descending.
+// three mantissa bits), descending, in one workgroup with the counters in
+// LDS (the radii crowd into a few buckets, which made global atomics
+// serialise).  The same launch clears the search's counters.
 constexpr int kOrderBuckets = 2048;
-__global__ void k_order_keys(const float *__restrict__ lam, int first_leaf, int n_leaves, int ng,
-                             int n_waves, int *__restrict__ bucket, int *__restrict__ count) {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= n_waves) return;
+__device__ inline int order_bucket(const float *__restrict__ lam, int first_leaf, int n_leaves,
+                                   int ng, int w) {
     float r = 0.f;
     for (int g = 0; g < ng; ++g) {
         const int leaf = w * ng + g;
         if (leaf < n_leaves) r = fmaxf(r, lam[first_leaf + leaf]);
     }
-    const int b = kOrderBuckets - 1 - min(kOrderBuckets - 1, int(__float_as_uint(fmaxf(r, 0.f)) >> 20));
-    bucket[w] = b;
-    atomicAdd(&count[b], 1);
+    return kOrderBuckets - 1 - min(kOrderBuckets - 1, int(__float_as_uint(fmaxf(r, 0.f)) >> 20));
 }
-__global__ __launch_bounds__(1024) void k_order_scan(int *__restrict__ count) {
-    __shared__ int sc[1024];
+__global__ __launch_bounds__(1024) void k_order(const float *__restrict__ lam, int first_leaf,
+                                                int n_leaves, int ng, int n_waves,
+                                                int *__restrict__ order,
+                                                unsigned long long *__restrict__ zero, int n_zero) {
+    __shared__ int cnt[kOrderBuckets];
+    __shared__ int part[1024];
     const int t = threadIdx.x;
-    const int c0 = count[2 * t], c1 = count[2 * t + 1];
-    sc[t] = c0 + c1;
+    for (int i = t; i < kOrderBuckets; i += 1024) cnt[i] = 0;
+    for (int i = t; i < n_zero; i += 1024) zero[i] = 0;
+    __syncthreads();
+    for (int w = t; w < n_waves; w += 1024)
+        atomicAdd(&cnt[order_bucket(lam, first_leaf, n_leaves, ng, w)], 1);
+    __syncthreads();
+    // exclusive scan: two buckets per thread, then across threads
+    const int c0 = cnt[2 * t], c1 = cnt[2 * t + 1];
+    part[t] = c0 + c1;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        const int v = t >= off ? sc[t - off] : 0;
+        const int v = t >= off ? part[t - off] : 0;
         __syncthreads();
-        sc[t] += v;
+        part[t] += v;
         __syncthreads();
     }
-    const int excl = sc[t] - c0 - c1;
-    count[2 * t] = excl;  // becomes the bucket's cursor
-    count[2 * t + 1] = excl + c0;
-}
-__global__ void k_order_scatter(const int *__restrict__ bucket, int n_waves, int *__restrict__ cursor,
-                                int *__restrict__ order) {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= n_waves) return;
-    order[atomicAdd(&cursor[bucket[w]], 1)] = w;
+    const int excl = part[t] - c0 - c1;
+    cnt[2 * t] = excl;
+    cnt[2 * t + 1] = excl + c0;
+    __syncthreads();
+    for (int w = t; w < n_waves; w += 1024)
+        order[atomicAdd(&cnt[order_bucket(lam, first_leaf, n_leaves, ng, w)], 1)] = w;
 }
 
 struct Scratch {
@@ -108,7 +114,7 @@ struct Scratch {
         return e;
     }
     ~Scratch() {
-        for (void *q : p) free_async(q, s);
+        dev_free_many(p.data(), int(p.size()), s);
     }
 };
 
@@ -146,6 +152,7 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     int max_leaf = int((qt->n + qt->n_leaves - 1) / qt->n_leaves);
     int lpl_log2 = 0;
     while ((1 << lpl_log2) < max_leaf) ++lpl_log2;
+    if (lpl_log2 < 3) lpl_log2 = 3;  // the FP32 kernels take 8..64 lanes per leaf
     if (qt->dp >= 32) lpl_log2 = 6;
     const bool bf16 = opts.precision == KNN_PREC_BF16;
     if (bf16) {
@@ -160,10 +167,7 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
 
     Scratch sc{s, {}};
     unsigned long long *dstats = nullptr;
-    if (opts.stats) {
-        KNN_HIP(sc.get(&dstats, 2 * ST_COUNT));
-        KNN_HIP(hipMemsetAsync(dstats, 0, 2 * ST_COUNT * sizeof(unsigned long long), s));
-    }
+    if (opts.stats) KNN_HIP(sc.get(&dstats, 2 * ST_COUNT));  // cleared before the launch
     int *fb_flag = nullptr, *fb_count = nullptr;
     float *fb_bound = nullptr;
     if (opts.seed_radius) {
@@ -216,17 +220,13 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     // (the stride-64 BF16 kernel sweeps reference leaves per workgroup of
     // four query leaves and takes no order)
     if ((!bf16 || ref->dp < 64) && waves > 1) {
-        int *order = nullptr, *bucket = nullptr, *count = nullptr;
+        int *order = nullptr;
         KNN_HIP(sc.get(&order, waves));
-        KNN_HIP(sc.get(&bucket, waves));
-        KNN_HIP(sc.get(&count, kOrderBuckets));
-        KNN_HIP(hipMemsetAsync(count, 0, kOrderBuckets * sizeof(int), s));
-        const int nb = (waves + 255) / 256;
-        k_order_keys<<<nb, 256, 0, s>>>(qt->lam, int(qt->first_leaf), nq_leaves, NG, waves, bucket,
-                                        count);
-        k_order_scan<<<1, 1024, 0, s>>>(count);
-        k_order_scatter<<<nb, 256, 0, s>>>(bucket, waves, count, order);
+        k_order<<<1, 1024, 0, s>>>(qt->lam, int(qt->first_leaf), nq_leaves, NG, waves, order,
+                                   dstats, dstats ? 2 * ST_COUNT : 0);
         a.order = order;
+    } else if (dstats) {
+        KNN_HIP(hipMemsetAsync(dstats, 0, 2 * ST_COUNT * sizeof(unsigned long long), s));
     }
     hipEvent_t ev[4];
     for (auto &e : ev) KNN_HIP(hipEventCreate(&e));
@@ -354,6 +354,17 @@ knn_status knn_build_tree_pair(const float *ref_points, int64_t n_ref, const flo
     KNN_TRY(check_build_args("knn_build_tree_pair (query)", query_points, n_query, d, leaf_size));
     return build_tree_pair(ref_points, n_ref, query_points, n_query, d, leaf_size,
                            (hipStream_t)stream, ref_out, query_out);
+}
+
+knn_status knn_all_knn(const float *ref_points, int64_t n_ref, const float *query_points,
+                       int64_t n_query, int32_t d, int32_t leaf_size, int32_t k,
+                       const knn_opts *opts, int64_t *idx_out, float *dist_out, void *stream) {
+    set_error("");
+    KNN_TRY(check_build_args("knn_all_knn (reference)", ref_points, n_ref, d, leaf_size));
+    if (query_points)
+        KNN_TRY(check_build_args("knn_all_knn (query)", query_points, n_query, d, leaf_size));
+    return all_knn(ref_points, n_ref, query_points, n_query, d, leaf_size, k, opts, idx_out,
+                   dist_out, (hipStream_t)stream);
 }
 
 void knn_free_tree(knn_tree *tree) { free_tree(tree); }

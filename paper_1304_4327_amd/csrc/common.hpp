@@ -123,6 +123,21 @@ template <class Op>
 __device__ inline float reduce32(float v, Op op) { return xor16_op(reduce16(v, op), op); }
 template <class Op>
 __device__ inline float reduce64(float v, Op op) { return xor32_op(reduce32(v, op), op); }
+// one step of a lane-group reduction: combines each lane with its partner at
+// level l (lane ^ (1 << l) for l = 0, 1, 4, 5; for l = 2, 3 the mirrored lane
+// of the same 8 / 16, which is the same partner group once levels below l are
+// reduced).  l is wave-uniform, so the switch is a scalar branch.
+template <class Op>
+__device__ inline float xor_level(float v, int l, Op op) {
+    switch (l) {
+        case 0: return op(v, dpp_f<0xB1>(v));
+        case 1: return op(v, dpp_f<0x4E>(v));
+        case 2: return op(v, dpp_f<0x141>(v));
+        case 3: return op(v, dpp_f<0x140>(v));
+        case 4: return op(v, __shfl_xor(v, 16));
+        default: return op(v, __shfl_xor(v, 32));
+    }
+}
 struct OpAdd {
     __device__ float operator()(float a, float b) const { return a + b; }
 };
@@ -140,11 +155,19 @@ knn_status build_tree(const float *points, int64_t n, int d, int leaf, hipStream
 knn_status build_tree_pair(const float *pa, int64_t na, const float *pb, int64_t nb, int d,
                            int leaf, hipStream_t s, knn_tree **out_a, knn_tree **out_b);
 void free_tree(knn_tree *t);
+// builds (overlapped when query_points is given), search, frees (tree_build.hip)
+knn_status all_knn(const float *ref_points, int64_t n_ref, const float *query_points,
+                   int64_t n_query, int d, int leaf, int k, const knn_opts *opts,
+                   int64_t *idx_out, float *dist_out, hipStream_t s);
+// the search of an existing pair of trees (api.hip)
+knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_opts *opts,
+                  int64_t *idx_out, float *dist_out, hipStream_t s);
 
 // Device memory for trees and scratch comes from the library's caching
 // allocator (memory.hip): stream-ordered reuse of released blocks.
 hipError_t dev_alloc(void **p, size_t bytes, hipStream_t s);
 void dev_free(void *p, hipStream_t s);
+void dev_free_many(void *const *ps, int n, hipStream_t s);  // one event for all
 hipError_t release_cached();
 size_t cached_bytes();
 template <class T>

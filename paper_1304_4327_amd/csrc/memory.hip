@@ -5,7 +5,8 @@
 // microseconds per call.  A build or a search takes a dozen buffers, so the
 // library keeps released blocks on a per-device free list and hands them out
 // again:
-//   * a block released on stream s is recorded with an event on s;
+//   * a block released on stream s is recorded with an event on s (blocks
+//     released together share one event, counted by reference);
 //   * a later request on the same stream takes it at once (stream order puts
 //     the new work after everything queued before the release);
 //   * a request on another stream first makes its stream wait for the event.
@@ -22,13 +23,27 @@
 namespace knnx {
 namespace {
 
+// an event shared by the blocks of one release
+struct SharedEvent {
+    hipEvent_t ev = nullptr;
+    int refs = 0;
+};
+
 struct Block {
     void *p = nullptr;
     size_t bytes = 0;
     int device = 0;
     hipStream_t stream = nullptr;  // stream of the last release
-    hipEvent_t ready = nullptr;    // recorded on that stream at release
+    SharedEvent *ready = nullptr;  // recorded on that stream at release
 };
+
+void drop_ref(SharedEvent *&r) {
+    if (r && --r->refs == 0) {
+        (void)hipEventDestroy(r->ev);
+        delete r;
+    }
+    r = nullptr;
+}
 
 constexpr int kMaxDevices = 64;
 
@@ -55,9 +70,9 @@ hipError_t drain_device(Cache &c, int dev) {
     for (auto &kv : c.free_blocks[dev]) {
         Block &b = kv.second;
         if (b.ready) {
-            hipError_t e = hipEventSynchronize(b.ready);
+            hipError_t e = hipEventSynchronize(b.ready->ev);
             if (first == hipSuccess) first = e;
-            (void)hipEventDestroy(b.ready);
+            drop_ref(b.ready);
         }
         hipError_t e = hipFree(b.p);
         if (first == hipSuccess) first = e;
@@ -84,12 +99,13 @@ hipError_t dev_alloc(void **out, size_t bytes, hipStream_t s) {
         Block b = it->second;
         fl.erase(it);
         if (b.ready && b.stream != s) {
-            e = hipStreamWaitEvent(s, b.ready, 0);
+            e = hipStreamWaitEvent(s, b.ready->ev, 0);
             if (e != hipSuccess) {
                 fl.emplace(b.bytes, b);
                 return e;
             }
         }
+        drop_ref(b.ready);
         c.live.emplace(b.p, b);
         *out = b.p;
         return hipSuccess;
@@ -111,28 +127,41 @@ hipError_t dev_alloc(void **out, size_t bytes, hipStream_t s) {
     return hipSuccess;
 }
 
-void dev_free(void *p, hipStream_t s) {
-    if (!p) return;
+void dev_free_many(void *const *ps, int n, hipStream_t s) {
     Cache &c = cache();
     std::lock_guard<std::mutex> lock(c.mu);
-    auto it = c.live.find(p);
-    if (it == c.live.end()) return;  // not ours: ignore rather than corrupt the lists
-    Block b = it->second;
-    c.live.erase(it);
-    int cur = 0;
-    const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != b.device;
-    if (switch_dev) (void)hipSetDevice(b.device);
-    if (!b.ready) (void)hipEventCreateWithFlags(&b.ready, hipEventDisableTiming);
-    b.stream = s;
-    if (!b.ready || hipEventRecord(b.ready, s) != hipSuccess) {
-        // no event: the block can only be reused after the device is idle
-        (void)hipStreamSynchronize(s);
-        if (b.ready) (void)hipEventDestroy(b.ready);
-        b.ready = nullptr;
+    SharedEvent *ev = nullptr;  // created on the first block that needs it
+    bool synced = false;
+    for (int i = 0; i < n; ++i) {
+        if (!ps[i]) continue;
+        auto it = c.live.find(ps[i]);
+        if (it == c.live.end()) continue;  // not ours: ignore rather than corrupt the lists
+        Block b = it->second;
+        c.live.erase(it);
+        b.stream = s;
+        if (!ev && !synced) {
+            int cur = 0;
+            const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != b.device;
+            if (switch_dev) (void)hipSetDevice(b.device);
+            ev = new SharedEvent();
+            if (hipEventCreateWithFlags(&ev->ev, hipEventDisableTiming) != hipSuccess ||
+                hipEventRecord(ev->ev, s) != hipSuccess) {
+                // no event: the blocks can only be reused after the stream is idle
+                if (ev->ev) (void)hipEventDestroy(ev->ev);
+                delete ev;
+                ev = nullptr;
+                (void)hipStreamSynchronize(s);
+                synced = true;
+            }
+            if (switch_dev) (void)hipSetDevice(cur);
+        }
+        b.ready = ev;
+        if (ev) ++ev->refs;
+        c.free_blocks[b.device].emplace(b.bytes, b);
     }
-    if (switch_dev) (void)hipSetDevice(cur);
-    c.free_blocks[b.device].emplace(b.bytes, b);
 }
+
+void dev_free(void *p, hipStream_t s) { dev_free_many(&p, 1, s); }
 
 hipError_t release_cached() {
     Cache &c = cache();

@@ -70,7 +70,7 @@ __device__ inline double d2_fp64(const float (&q)[D], const float *r) {
     return s;
 }
 
-template <int D, int K>
+template <int D, int K, int LG>
 __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     constexpr int DP = stride_for(D);
     constexpr bool RESCORE = D > 8;
@@ -78,8 +78,8 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     constexpr float kSlack = 1.0f + 0x1p-16f;            // prune slack (squared)
     constexpr float kGamma = 1.0f + (D + 6) * 0x1p-24f;  // FP32 filter slack
     const int lane = threadIdx.x & 63;
-    const int lpl_log2 = a.lpl_log2;
-    const int NG = 64 >> lpl_log2;
+    constexpr int lpl_log2 = LG;
+    constexpr int NG = 64 >> lpl_log2;
     const int n_list = a.q_n_leaves;
     int wave;
     if (a.order) {
@@ -120,9 +120,10 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         for (int j = 0; j < D; ++j) {
             float lo = has_leaf ? qb[j] : kInf;
             float hi = has_leaf ? qb[DP + j] : -kInf;
-            for (int off = (1 << lpl_log2); off < 64; off <<= 1) {
-                lo = fminf(lo, __shfl_xor(lo, off));
-                hi = fmaxf(hi, __shfl_xor(hi, off));
+#pragma unroll
+            for (int l = lpl_log2; l < 6; ++l) {
+                lo = xor_level(lo, l, OpMin());
+                hi = xor_level(hi, l, OpMax());
             }
             ulo[j] = lo;
             uhi[j] = hi;
@@ -158,6 +159,12 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     uint64_t n_pairs = 0;
     const int n_valid = __popcll(ballot(valid));
 
+    // Prefetch into the scalar cache: a few scalar loads of lines that the
+    // next steps will read, issued together with loads that are waited for
+    // anyway.  Their values are folded into tacc one step later (a use at
+    // once would make the wave wait for them) and reach a store that never
+    // happens, so the compiler keeps them.
+    uint32_t tacc = 0, q0 = 0, q1 = 0, q2 = 0;
     // per-point bound: min(D_p[k], B(leaf)); +inf without pruning
     auto point_bound2 = [&]() -> float {
         return a.bound == KNN_BOUND_NONE ? kInf : fminf(bound2, dist[K - 1]);
@@ -197,8 +204,26 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     auto score_children = [&](int c0, bool &k0, bool &k1, float &m0, float &m1) {
         n_score += 2;
         const float *b = a.rbox + int64_t(c0) * 2 * DP;
+        // prefetch, issued with the children's box loads: the four
+        // grandchildren's boxes (contiguous), or the first lines of both
+        // leaves' tiles
+        uint32_t p0 = 0, p1 = 0, p2 = 0;
+        if constexpr (DP <= 4) {
+            const bool inner = c0 < a.r_first_leaf;
+            const float *g = inner ? a.rbox + int64_t(2 * c0 + 1) * 2 * DP
+                                   : a.rlpts + int64_t(c0 - a.r_first_leaf) * a.r_leaf_slots * DP;
+            const int s1 = inner ? 16 : a.r_leaf_slots * DP;
+            const int s2 = inner ? 8 * DP - 1 : a.r_leaf_slots * DP + 16;
+            p0 = __float_as_uint(g[0]);
+            p1 = __float_as_uint(g[s1]);
+            p2 = __float_as_uint(g[s2]);
+        }
         k0 = score_box(b, m0);
         k1 = score_box(b + 2 * DP, m1);
+        tacc ^= q0 ^ q1 ^ q2;
+        q0 = p0;
+        q1 = p1;
+        q2 = p2;
     };
 
     auto insert = [&](float x, int id) {
@@ -229,25 +254,31 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     }
     lam2_anc[0] = lam2;
 
+    // refresh of B(N_q) after a tile.  The group reductions step through
+    // the lane levels 0 .. lpl_log2-1 (uniform branches: DPP inside a row,
+    // a shuffle across rows); the B(Par) terms continue one level per
+    // ancestor.  The square root is the hardware one (about 1 ulp): its
+    // error is far inside the prune slack.
     auto refresh_bound = [&]() {
         if (a.bound == KNN_BOUND_NONE) return;
         float hi = valid ? dist[K - 1] : -kInf;
         float lo = valid ? dist[K - 1] : kInf;
-        for (int off = (1 << lpl_log2) >> 1; off > 0; off >>= 1) {
-            hi = fmaxf(hi, __shfl_xor(hi, off));
-            lo = fminf(lo, __shfl_xor(lo, off));
+#pragma unroll
+        for (int l = 0; l < lpl_log2; ++l) {
+            hi = xor_level(hi, l, OpMax());
+            lo = xor_level(lo, l, OpMin());
         }
         float b = hi;  // B1^2
         if (a.bound == KNN_BOUND_B) {
-            const float b2 = sqrtf(lo) + lam2;
+            const float b2 = __builtin_amdgcn_sqrtf(lo) + lam2;
             b = fminf(b, b2 * b2);
             if (par_ok) {
 #pragma unroll
                 for (int s = 1; s <= 5; ++s) {
-                    const int off = (1 << lpl_log2) << (s - 1);
-                    if (off < 64) {
-                        lo = fminf(lo, __shfl_xor(lo, off));
-                        const float bp = sqrtf(lo) + lam2_anc[s];
+                    const int l = lpl_log2 + s - 1;
+                    if (l < 6) {
+                        lo = xor_level(lo, l, OpMin());
+                        const float bp = __builtin_amdgcn_sqrtf(lo) + lam2_anc[s];
                         b = fminf(b, bp * bp);
                     }
                 }
@@ -256,6 +287,10 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         bound2 = fminf(b, seed2);
     };
 
+    // BaseCase over one reference leaf: every lane against each reference
+    // point, CH points per batch.  A candidate must beat min(D_p[k], B):
+    // B bounds the point's final k-th distance, so anything farther cannot
+    // enter its final list (equal distances aside).
     // BaseCase over one reference leaf: every lane against each reference
     // point, CH points per batch.  A candidate must beat min(D_p[k], B):
     // B bounds the point's final k-th distance, so anything farther cannot
@@ -269,6 +304,14 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         const float *rp = a.rlpts + int64_t(node - a.r_first_leaf) * a.r_leaf_slots * DP;
         n_pairs += uint64_t(cnt) * uint64_t(n_valid);
         const float bnd = bound2 * kSlack;
+        uint32_t r0 = 0, r1 = 0, r2 = 0;
+        if constexpr (DP <= 4) {
+            // the tile's later 64-byte lines, fetched with the first batch
+            const int last = max(cnt * DP - 1, 0);
+            r0 = __float_as_uint(rp[min(32, last)]);
+            r1 = __float_as_uint(rp[min(64, last)]);
+            r2 = __float_as_uint(rp[min(96, last)]);
+        }
         for (int t0 = 0; t0 < cnt; t0 += CH) {
             float sd[CH];
 #pragma unroll
@@ -309,6 +352,7 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
                 }
             }
         }
+        tacc ^= r0 ^ r1 ^ r2;
         refresh_bound();
     };
 
@@ -319,47 +363,58 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         uint64_t nearbits = 0;
         bool down = score(0, dm0);
         if (down) {
+            // outer loop: one reference leaf per iteration; the inner walk
+            // leaves the k-lists untouched, so they are not carried through
+            // its loop (carried through one loop with the tile, the compiler
+            // moved every list register on every walk step)
             for (;;) {
-                if (down) {
-                    if (node >= a.r_first_leaf) {
-                        tile(node);
-                        down = false;
-                        continue;
-                    }
-                    const int c0 = 2 * node + 1, c1 = c0 + 1;
-                    bool k0, k1;
-                    score_children(c0, k0, k1, dm0, dm1);
-                    if (!k0 && !k1) {
-                        down = false;
-                        continue;
-                    }
-                    const bool right = k1 && (!k0 || dm1 < dm0);
-                    if (right)
-                        nearbits |= (uint64_t(1) << depth);
-                    else
-                        nearbits &= ~(uint64_t(1) << depth);
-                    node = uniform_i(right ? c1 : c0);
-                    ++depth;
-                } else {
-                    if (node == 0) break;
-                    --depth;
-                    const bool is_right = (node & 1) == 0;
-                    const bool near_right = (nearbits >> depth) & 1;
-                    if (is_right == near_right) {
-                        const int far = is_right ? node - 1 : node + 1;
-                        if (score(far, dm0)) {
-                            node = far;
-                            ++depth;
-                            down = true;
+                bool leaf = false;
+                for (;;) {
+                    if (down) {
+                        if (node >= a.r_first_leaf) {
+                            leaf = true;
+                            break;
+                        }
+                        const int c0 = 2 * node + 1, c1 = c0 + 1;
+                        bool k0, k1;
+                        score_children(c0, k0, k1, dm0, dm1);
+                        if (!k0 && !k1) {
+                            down = false;
                             continue;
                         }
+                        const bool right = k1 && (!k0 || dm1 < dm0);
+                        if (right)
+                            nearbits |= (uint64_t(1) << depth);
+                        else
+                            nearbits &= ~(uint64_t(1) << depth);
+                        node = uniform_i(right ? c1 : c0);
+                        ++depth;
+                    } else {
+                        if (node == 0) break;
+                        --depth;
+                        const bool is_right = (node & 1) == 0;
+                        const bool near_right = (nearbits >> depth) & 1;
+                        if (is_right == near_right) {
+                            const int far = is_right ? node - 1 : node + 1;
+                            if (score(far, dm0)) {
+                                node = far;
+                                ++depth;
+                                down = true;
+                                continue;
+                            }
+                        }
+                        node = uniform_i((node - 1) >> 1);
                     }
-                    node = uniform_i((node - 1) >> 1);
                 }
+                if (!leaf) break;
+                tile(node);
+                down = false;
             }
         }
     }
 
+    // keeps the prefetch loads (k >= 1 always)
+    if ((tacc ^ q0 ^ q1 ^ q2) == 0x7fc00001u && a.k < 0) a.out_idx[0] = 0;
     // ---- write-out: FP64 re-score of the final list, order by (d, index) ----
     // Each entry becomes its output key in place: the FP32 distance from the
     // FP64 re-score and the original index.  Padding slots (below K-kk),
@@ -395,11 +450,9 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     // a proven bound for the fallback pass: min over full lists of D_p[k]
     // plus 2 lambda (the B2 argument holds whatever seed built the lists)
     float fbb = (valid && worst < kInf) ? worst : kInf;
-    for (int off = (1 << lpl_log2) >> 1; off > 0; off >>= 1) {
-        worst = fmaxf(worst, __shfl_xor(worst, off));
-    }
+    for (int l = 0; l < lpl_log2; ++l) worst = xor_level(worst, l, OpMax());
     const uint64_t fbmask = ballot(fb);
-    for (int off = (1 << lpl_log2) >> 1; off > 0; off >>= 1) fbb = fminf(fbb, __shfl_xor(fbb, off));
+    for (int l = 0; l < lpl_log2; ++l) fbb = xor_level(fbb, l, OpMin());
     if (has_leaf && li == 0) {
         if (a.leaf_kth) a.leaf_kth[qleaf] = fmaxf(worst, 0.0f);
         if (a.fallback) {
@@ -435,28 +488,33 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     }
 }
 
+template <int D, int K>
+hipError_t launch_search_valu_k(const SearchArgs &a, int grid, hipStream_t s) {
+    switch (a.lpl_log2) {
+        case 3: k_search_valu<D, K, 3><<<grid, 256, 0, s>>>(a); break;
+        case 4: k_search_valu<D, K, 4><<<grid, 256, 0, s>>>(a); break;
+        case 5: k_search_valu<D, K, 5><<<grid, 256, 0, s>>>(a); break;
+        case 6: k_search_valu<D, K, 6><<<grid, 256, 0, s>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int D>
 hipError_t launch_search_valu(const SearchArgs &a, int K, int grid, hipStream_t s) {
     switch (K) {
-#define KNN_CASE(KK)                                                  \
-    case KK:                                                          \
-        k_search_valu<D, KK><<<grid, 256, 0, s>>>(a);                 \
-        break;
-        KNN_CASE(4)
-        KNN_CASE(5)
-        KNN_CASE(8)
-        KNN_CASE(11)
-        KNN_CASE(10)
-        KNN_CASE(16)
-        KNN_CASE(32)
-        KNN_CASE(50)
-        KNN_CASE(51)
-        KNN_CASE(64)
-#undef KNN_CASE
-        default:
-            return hipErrorInvalidValue;
+        case 4: return launch_search_valu_k<D, 4>(a, grid, s);
+        case 5: return launch_search_valu_k<D, 5>(a, grid, s);
+        case 8: return launch_search_valu_k<D, 8>(a, grid, s);
+        case 10: return launch_search_valu_k<D, 10>(a, grid, s);
+        case 11: return launch_search_valu_k<D, 11>(a, grid, s);
+        case 16: return launch_search_valu_k<D, 16>(a, grid, s);
+        case 32: return launch_search_valu_k<D, 32>(a, grid, s);
+        case 50: return launch_search_valu_k<D, 50>(a, grid, s);
+        case 51: return launch_search_valu_k<D, 51>(a, grid, s);
+        case 64: return launch_search_valu_k<D, 64>(a, grid, s);
+        default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace knnx

@@ -25,6 +25,8 @@
 // lambda gets an upper bound from the children.
 #include "common.hpp"
 
+#include <condition_variable>
+#include <functional>
 #include <mutex>
 #include <thread>
 
@@ -48,29 +50,44 @@ __device__ inline uint64_t lanemask_lt() {
     return (uint64_t(1) << (threadIdx.x & 63)) - 1;
 }
 
-__global__ void k_ranges(int2 *range, int n, int n_nodes) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_nodes) return;
-    unsigned v = unsigned(i) + 1u;
-    int depth = 31 - __clz(v);
-    int start = 0, cnt = n;
-    for (int l = depth - 1; l >= 0; --l) {
-        int half = cnt >> 1;
-        if ((v >> l) & 1u) {
-            start += half;
-            cnt -= half;
-        } else {
-            cnt = half;
-        }
+// Set-up of one build in a single launch: node ranges (heap order, the left
+// child takes floor(c/2) of a node's c points), the error flag, the
+// histogram and padding buffers cleared, the box accumulators initialised.
+struct PrepArgs {
+    int2 *range;
+    int n, n_nodes;
+    int *flag;
+    int *hist;
+    int64_t n_hist;
+    float *pad0, *pad1;  // padding rows to zero (either may be NULL)
+    int n_pad;
+    uint32_t *boxu;  // [seg][2][dp]: lo words all-ones, hi words zero
+    int n_box, dp;
+};
+__global__ void k_prep(const PrepArgs p) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i == 0) *p.flag = 0;
+    if (i < p.n_hist) p.hist[i] = 0;
+    if (i < p.n_pad) {
+        if (p.pad0) p.pad0[i] = 0.f;
+        if (p.pad1) p.pad1[i] = 0.f;
     }
-    range[i] = make_int2(start, cnt);
-}
-
-
-__global__ void k_fill_box(uint32_t *a, int n, int dp) {
-    // layout [seg][2][dp]: lo words start all-ones, hi words zero
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = ((i / dp) & 1) ? 0u : 0xffffffffu;
+    if (i < p.n_box) p.boxu[i] = ((i / p.dp) & 1) ? 0u : 0xffffffffu;
+    if (i < p.n_nodes) {
+        const unsigned v = unsigned(i) + 1u;
+        const int depth = 31 - __clz(v);
+        int start = 0, cnt = p.n;
+        for (int l = depth - 1; l >= 0; --l) {
+            const int half = cnt >> 1;
+            if ((v >> l) & 1u) {
+                start += half;
+                cnt -= half;
+            } else {
+                cnt = half;
+            }
+        }
+        p.range[i] = make_int2(start, cnt);
+    }
 }
 
 // ---- initial copy: padded rows in input order, non-finite check -------------
@@ -539,13 +556,22 @@ __global__ __launch_bounds__(kBlock) void k_level_scatter(const uint32_t *__rest
     }
 }
 
-// ---- one wave finishes a segment's subtree ------------------------------------
+// ---- one workgroup finishes a segment's subtree ---------------------------------
 // The segment's rows are contiguous in `cur`; for small strides they are
-// staged in LDS.  sidx holds local row numbers in the current order.  At the
-// end the rows are written in final (tree) order to `out_pts` and their
-// original indices to `out_perm`.
+// staged in LDS.  sidx holds local row numbers in the current order.  Each
+// of the four waves takes every fourth node of a level (a node is one wave's
+// work; its waits are wave-level), and the workgroup meets between levels.
+// At the end the rows are written in final (tree) order to `out_pts` and
+// their original indices to `out_perm`.
+constexpr int kLocalWaves = 4;
+__device__ inline void wave_lds_sync() {
+    // LDS writes of this wave visible to its other lanes; no workgroup wait
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 template <int DP>
-__global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ cur, int d,
+__global__ __launch_bounds__(64 * kLocalWaves) void k_local_build(const float *__restrict__ cur, int d,
                                                     const int *__restrict__ idx_glob,
                                                     const int2 *__restrict__ range, int l0,
                                                     int L, float *__restrict__ box,
@@ -554,16 +580,18 @@ __global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ cu
                                                     float *__restrict__ out_pts,
                                                     int *__restrict__ out_perm) {
     constexpr bool kLds = DP <= 8;
-    const int seg = blockIdx.x, lane = threadIdx.x;
+    const int seg = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int kThreads = 64 * kLocalWaves;
     const int2 rr = range[(1 << l0) - 1 + seg];
     const int base = rr.x, c = rr.y;
     __shared__ int sidx[2][kLocalMax];
     __shared__ uint32_t skey[kLocalMax];
-    __shared__ int hist[256];
+    __shared__ int hist_all[kLocalWaves][256];
+    int *hist = hist_all[wave];
     __shared__ float spts[kLds ? kLocalMax * DP : 4];
     const float *gpts = cur + int64_t(base) * DP;
     if constexpr (kLds) {
-        for (int t = lane; t < c * DP; t += 64) spts[t] = gpts[t];
+        for (int t = threadIdx.x; t < c * DP; t += kThreads) spts[t] = gpts[t];
     }
     auto X = [&](int row, int j) -> float {
         if constexpr (kLds)
@@ -571,14 +599,14 @@ __global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ cu
         else
             return gpts[int64_t(row) * DP + j];
     };
-    for (int e = lane; e < c; e += 64) sidx[0][e] = e;
+    for (int e = threadIdx.x; e < c; e += kThreads) sidx[0][e] = e;
     __syncthreads();
     int cb = 0;
     const int j_l = lane % DP, grp = lane / DP;
     constexpr int NG = 64 / DP;
     for (int lv = l0; lv < L; ++lv) {
         const int nsub = 1 << (lv - l0);
-        for (int sub = 0; sub < nsub; ++sub) {
+        for (int sub = wave; sub < nsub; sub += kLocalWaves) {
             const int node = (1 << lv) - 1 + seg * nsub + sub;
             const int2 nr = range[node];
             const int o = nr.x - base, cc = nr.y;
@@ -621,7 +649,7 @@ __global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ cu
             if (lane == 0) split_dim[node] = jsplit;
             // keys
             for (int e = lane; e < cc; e += 64) skey[o + e] = f2key(X(src[e], jsplit));
-            __syncthreads();
+            wave_lds_sync();
             const int m = cc / 2;
             int *dst = sidx[cb ^ 1] + o;
             // radix select of the key at rank floor(cc/2), 8-bit digits from
@@ -642,12 +670,12 @@ __global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ cu
                 hist[lane * 4 + 1] = 0;
                 hist[lane * 4 + 2] = 0;
                 hist[lane * 4 + 3] = 0;
-                __syncthreads();
+                wave_lds_sync();
                 for (int e = lane; e < cc; e += 64) {
                     uint32_t key = skey[o + e];
                     if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & dmask], 1);
                 }
-                __syncthreads();
+                wave_lds_sync();
                 const int h0 = hist[lane * 4 + 0], h1 = hist[lane * 4 + 1];
                 const int h2 = hist[lane * 4 + 2], h3 = hist[lane * 4 + 3];
                 const int sum = h0 + h1 + h2 + h3;
@@ -684,7 +712,7 @@ __global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ cu
                 mask |= dmask << shift;
                 rank = rem;
                 bits = shift;
-                __syncthreads();
+                wave_lds_sync();
             }
             // stable partition into the other buffer
             int run_l = 0, run_e = 0;
@@ -709,13 +737,14 @@ __global__ __launch_bounds__(64) void k_local_build(const float *__restrict__ cu
                 run_l += __popcll(bl);
                 run_e += __popcll(be);
             }
-            __syncthreads();
+            wave_lds_sync();
         }
+        __syncthreads();  // the next level reads every node's partition
         cb ^= 1;
     }
     // final order: rows and original indices
-    for (int e = lane; e < c; e += 64) out_perm[base + e] = idx_glob[base + sidx[cb][e]];
-    for (int t = lane; t < c * DP; t += 64) {
+    for (int e = threadIdx.x; e < c; e += kThreads) out_perm[base + e] = idx_glob[base + sidx[cb][e]];
+    for (int t = threadIdx.x; t < c * DP; t += kThreads) {
         const int e = t / DP, j = t % DP;
         out_pts[int64_t(base + e) * DP + j] = X(sidx[cb][e], j);
     }
@@ -868,7 +897,7 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
         hipStream_t s;
         std::vector<void *> p;
         ~Guard() {
-            for (void *q : p) free_async(q, s);
+            dev_free_many(p.data(), int(p.size()), s);
         }
     } g{s, {}};
     auto get = [&](auto **ptr, size_t cnt) -> hipError_t {
@@ -879,13 +908,6 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
     const size_t rows = size_t(n) + kPadRows;
     KNN_HIP(get(&idxA, n));
     KNN_HIP(get(&cur, rows * DP));
-    KNN_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
-
-    k_ranges<<<(n_nodes + 255) / 256, 256, 0, s>>>(t->range, nn, n_nodes);
-    {
-        const int64_t tot = int64_t(rows) * DP;
-        k_init<DP><<<int((tot + 255) / 256), 256, 0, s>>>(points, n, d, cur, idxA, flag);
-    }
 
     auto cmax = [&](int lv) { return int((n + (int64_t(1) << lv) - 1) >> lv); };
     int n_global = 0, maxseg = 1, maxblk = 1;
@@ -902,11 +924,26 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
         KNN_HIP(get(&sel, 4 * size_t(maxseg)));
         KNN_HIP(get(&hist, 3 * size_t(maxseg) * kBins));
         KNN_HIP(get(&counts, size_t(maxblk)));
-        KNN_HIP(hipMemsetAsync(hist, 0, 3 * size_t(maxseg) * kBins * sizeof(int), s));
-        // boxu: lo words all-ones, hi words zero
-        const int nbox = maxseg * 2 * DP;
-        k_fill_box<<<(nbox + 255) / 256, 256, 0, s>>>(boxu, nbox, DP);
-        KNN_HIP(hipMemsetAsync(nxt + size_t(n) * DP, 0, size_t(kPadRows) * DP * sizeof(float), s));
+    }
+    {
+        PrepArgs p{};
+        p.range = t->range;
+        p.n = nn;
+        p.n_nodes = n_nodes;
+        p.flag = flag;
+        p.hist = hist;
+        p.n_hist = n_global > 0 ? 3 * int64_t(maxseg) * kBins : 0;
+        p.pad0 = t->pts + size_t(n) * DP;
+        p.pad1 = n_global > 0 ? nxt + size_t(n) * DP : nullptr;
+        p.n_pad = kPadRows * DP;
+        p.boxu = boxu;
+        p.n_box = n_global > 0 ? maxseg * 2 * DP : 0;
+        p.dp = DP;
+        const int64_t tot = std::max<int64_t>({p.n_hist, int64_t(p.n_pad), int64_t(p.n_box),
+                                              int64_t(n_nodes), 1});
+        k_prep<<<int((tot + 255) / 256), 256, 0, s>>>(p);
+        const int64_t tot_init = int64_t(rows) * DP;
+        k_init<DP><<<int((tot_init + 255) / 256), 256, 0, s>>>(points, n, d, cur, idxA, flag);
     }
     int *H[3] = {hist, hist + size_t(maxseg) * kBins, hist + 2 * size_t(maxseg) * kBins};
     Sel *S[4] = {sel, sel + maxseg, sel + 2 * maxseg, sel + 3 * maxseg};
@@ -932,8 +969,7 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
         std::swap(cur, nxt);
     }
     if (n_global < L) {
-        KNN_HIP(hipMemsetAsync(t->pts + size_t(n) * DP, 0, size_t(kPadRows) * DP * sizeof(float), s));
-        k_local_build<DP><<<1 << n_global, 64, 0, s>>>(cur, d, idxA, t->range, n_global, L, t->box,
+        k_local_build<DP><<<1 << n_global, 64 * kLocalWaves, 0, s>>>(cur, d, idxA, t->range, n_global, L, t->box,
                                                        t->split_dim, flag, t->pts, t->perm);
     } else {
         // no split below the root (n <= leaf size): tree order = input order
@@ -969,13 +1005,8 @@ void free_tree(knn_tree *t) {
     int cur = 0;
     const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != t->device;
     if (switch_dev) (void)hipSetDevice(t->device);
-    free_async(t->pts, t->stream);
-    free_async(t->lpts, t->stream);
-    free_async(t->perm, t->stream);
-    free_async(t->range, t->stream);
-    free_async(t->box, t->stream);
-    free_async(t->lam, t->stream);
-    free_async(t->split_dim, t->stream);
+    void *blocks[] = {t->pts, t->lpts, t->perm, t->range, t->box, t->lam, t->split_dim};
+    dev_free_many(blocks, 7, t->stream);
     if (switch_dev) (void)hipSetDevice(cur);
     delete t;
 }
@@ -1034,7 +1065,6 @@ knn_status build_enqueue(const float *points, int64_t n, int d, int leaf, hipStr
     }
     e = hipEventCreate(&job.ev0);
     e = e ? e : hipEventCreate(&job.ev1);
-    e = e ? e : hipMemsetAsync(job.flag, 0, sizeof(int), s);
     e = e ? e : hipEventRecord(job.ev0, s);
     if (e != hipSuccess) {
         drop_job(job);
@@ -1081,6 +1111,50 @@ knn_status build_finish(BuildJob &job, knn_tree **out) {
     return KNN_OK;
 }
 
+// A helper thread that issues the second build of a pair.  It lives for the
+// whole process (never joined: it waits for work on a condition variable),
+// so a pair build costs no thread start.  One pair build uses it at a time;
+// a concurrent caller starts a thread of its own.
+class BuildHelper {
+  public:
+    static BuildHelper &get() {
+        static BuildHelper *h = new BuildHelper();  // never destroyed
+        return *h;
+    }
+    std::mutex use;  // held by the pair build that owns the helper
+    void run(std::function<void()> f) {
+        std::lock_guard<std::mutex> lock(mu_);
+        task_ = std::move(f);
+        pending_ = true;
+        cv_.notify_all();
+    }
+    void wait() {
+        std::unique_lock<std::mutex> lock(mu_);
+        cv_.wait(lock, [&] { return !pending_; });
+    }
+
+  private:
+    BuildHelper() { std::thread([this] { loop(); }).detach(); }
+    void loop() {
+        for (;;) {
+            std::function<void()> f;
+            {
+                std::unique_lock<std::mutex> lock(mu_);
+                cv_.wait(lock, [&] { return pending_; });
+                f = std::move(task_);
+            }
+            f();
+            std::lock_guard<std::mutex> lock(mu_);
+            pending_ = false;
+            cv_.notify_all();
+        }
+    }
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::function<void()> task_;
+    bool pending_ = false;
+};
+
 // a second stream per device (default priority) for the pair build
 hipError_t aux_stream(hipStream_t *out) {
     constexpr int kMaxDevices = 64;
@@ -1108,8 +1182,13 @@ knn_status build_tree(const float *points, int64_t n, int d, int leaf, hipStream
     return build_finish(job, out);
 }
 
-knn_status build_tree_pair(const float *pa, int64_t na, const float *pb, int64_t nb, int d,
-                           int leaf, hipStream_t s, knn_tree **out_a, knn_tree **out_b) {
+namespace {
+
+// enqueues the builds of a and (when pb is not NULL) b, b on the second
+// stream from the helper thread; on error nothing is left queued or held
+knn_status pair_enqueue(const float *pa, int64_t na, const float *pb, int64_t nb, int d, int leaf,
+                        hipStream_t s, BuildJob &ja, BuildJob &jb) {
+    if (!pb) return build_enqueue(pa, na, d, leaf, s, ja);
     hipStream_t s2;
     KNN_HIP(aux_stream(&s2));
     // the second build may only start once the caller's stream has produced
@@ -1122,12 +1201,11 @@ knn_status build_tree_pair(const float *pa, int64_t na, const float *pb, int64_t
     if (e != hipSuccess) return hip_fail(e, "knn_build_tree_pair: stream join", __FILE__, __LINE__);
     // the launches of one build take about as long to issue as to run, so
     // the second build is issued from a second host thread
-    BuildJob ja, jb;
     int dev = 0;
     KNN_HIP(hipGetDevice(&dev));
     knn_status sb = KNN_OK;
     std::string msg_b;
-    std::thread worker([&] {
+    auto second = [&] {
         if (hipSetDevice(dev) != hipSuccess) {
             sb = KNN_E_DEVICE;
             msg_b = "knn_build_tree_pair: hipSetDevice failed in the build thread";
@@ -1135,32 +1213,80 @@ knn_status build_tree_pair(const float *pa, int64_t na, const float *pb, int64_t
         }
         sb = build_enqueue(pb, nb, d, leaf, s2, jb);
         if (sb != KNN_OK) msg_b = get_error();
-    });
-    const knn_status sa0 = build_enqueue(pa, na, d, leaf, s, ja);
-    const std::string msg_a0 = get_error();
-    worker.join();
-    if (sa0 != KNN_OK || sb != KNN_OK) {
+    };
+    BuildHelper &helper = BuildHelper::get();
+    std::unique_lock<std::mutex> owner(helper.use, std::try_to_lock);
+    std::thread own;
+    if (owner.owns_lock())
+        helper.run(second);
+    else
+        own = std::thread(second);
+    const knn_status sa = build_enqueue(pa, na, d, leaf, s, ja);
+    const std::string msg_a = get_error();
+    if (owner.owns_lock())
+        helper.wait();
+    else
+        own.join();
+    if (sa != KNN_OK || sb != KNN_OK) {
         knn_tree *tmp = nullptr;
-        if (sa0 == KNN_OK && build_finish(ja, &tmp) == KNN_OK) free_tree(tmp);
+        if (sa == KNN_OK && build_finish(ja, &tmp) == KNN_OK) free_tree(tmp);
         tmp = nullptr;
         if (sb == KNN_OK && build_finish(jb, &tmp) == KNN_OK) free_tree(tmp);
-        return sa0 != KNN_OK ? fail(sa0, msg_a0) : fail(sb, msg_b);
+        return sa != KNN_OK ? fail(sa, msg_a) : fail(sb, msg_b);
     }
-    knn_tree *ta = nullptr, *tb = nullptr;
-    const knn_status sa = build_finish(ja, &ta);
+    return KNN_OK;
+}
+
+// waits for both builds; on error neither tree is returned
+knn_status pair_finish(BuildJob &ja, BuildJob &jb, hipStream_t s, knn_tree **ta, knn_tree **tb) {
+    const bool two = jb.t != nullptr;
+    knn_tree *a = nullptr, *b = nullptr;
+    const knn_status sa = build_finish(ja, &a);
     const std::string msg_a = get_error();
-    const knn_status sb2 = build_finish(jb, &tb);
-    if (sa != KNN_OK || sb2 != KNN_OK) {
-        if (ta) free_tree(ta);
-        if (tb) free_tree(tb);
-        return sa != KNN_OK ? fail(sa, msg_a) : sb2;
+    const knn_status sb = two ? build_finish(jb, &b) : KNN_OK;
+    if (sa != KNN_OK || sb != KNN_OK) {
+        if (a) free_tree(a);
+        if (b) free_tree(b);
+        return sa != KNN_OK ? fail(sa, msg_a) : sb;
     }
     // both builds have completed (finish waited for each stream); the second
     // tree belongs to the caller's stream from now on
-    tb->stream = s;
-    *out_a = ta;
-    *out_b = tb;
+    if (b) b->stream = s;
+    *ta = a;
+    if (tb) *tb = b;
     return KNN_OK;
+}
+
+}  // namespace
+
+knn_status build_tree_pair(const float *pa, int64_t na, const float *pb, int64_t nb, int d,
+                           int leaf, hipStream_t s, knn_tree **out_a, knn_tree **out_b) {
+    BuildJob ja, jb;
+    KNN_TRY(pair_enqueue(pa, na, pb, nb, d, leaf, s, ja, jb));
+    return pair_finish(ja, jb, s, out_a, out_b);
+}
+
+knn_status all_knn(const float *ref_points, int64_t n_ref, const float *query_points,
+                   int64_t n_query, int d, int leaf, int k, const knn_opts *opts,
+                   int64_t *idx_out, float *dist_out, hipStream_t s) {
+    BuildJob ja, jb;
+    KNN_TRY(pair_enqueue(ref_points, n_ref, query_points, n_query, d, leaf, s, ja, jb));
+    // the search reads the query tree built on the second stream
+    hipError_t e = jb.t ? hipStreamWaitEvent(s, jb.ev1, 0) : hipSuccess;
+    knn_status st = e == hipSuccess
+                        ? search(ja.t, jb.t, k, opts, idx_out, dist_out, s)
+                        : hip_fail(e, "knn_all_knn: stream join", __FILE__, __LINE__);
+    const std::string msg = get_error();
+    knn_tree *ta = nullptr, *tb = nullptr;
+    const knn_status sf = pair_finish(ja, jb, s, &ta, &tb);  // input checks of the builds
+    if (sf != KNN_OK) return sf;
+    if (st == KNN_OK && opts && opts->stats) {
+        opts->stats->ms_ref_build = ta->ms_build;
+        opts->stats->ms_query_build = tb ? tb->ms_build : 0.f;
+    }
+    free_tree(ta);
+    if (tb) free_tree(tb);
+    return st == KNN_OK ? KNN_OK : fail(st, msg);
 }
 
 }  // namespace knnx

@@ -46,7 +46,7 @@ class knn_stats(ctypes.Structure):
                 ("fallback_leaves", ctypes.c_int64), ("fallback_queries", ctypes.c_int64),
                 ("ms_query_build", ctypes.c_float), ("ms_search", ctypes.c_float),
                 ("ms_main_kernel", ctypes.c_float), ("n_query_leaves", ctypes.c_int32),
-                ("fallback_pairs", ctypes.c_int64)]
+                ("fallback_pairs", ctypes.c_int64), ("ms_ref_build", ctypes.c_float)]
 
 
 class knn_opts(ctypes.Structure):
@@ -84,6 +84,9 @@ _SIGS = {
     "knn_search": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts), _P, _P, _P]),
     "knn_search_points": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32,
                                          ctypes.POINTER(knn_opts), _P, _P, _P]),
+    "knn_all_knn": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(knn_opts), _P,
+                                   _P, _P]),
     "knn_mlp_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
     "knn_mlp_free": (None, [_P]),
     "knn_mlp_num_params": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
@@ -274,6 +277,36 @@ def knn_search_points(ref: Tree, queries, k: int, bound="B", precision="fp32",
     _check(load().knn_search_points(ref.handle, ctypes.c_void_p(queries.data_ptr()), nq,
                                     int(k), ctypes.byref(o), ctypes.c_void_p(idx.data_ptr()),
                                     ctypes.c_void_p(dist.data_ptr()), _stream(stream)))
+    return idx, dist, _stats_dict(st)
+
+
+def knn_all_knn(ref_points, query_points, k: int, leaf_size: int, bound="B", precision="fp32",
+                exclude_self=False, stats=False, out=None, stream=None):
+    """Build both trees (overlapped), search and free them in one call, with
+    one stream synchronisation (query_points None: ref_points on itself).
+
+    Returns (idx int64 [n_q, k], dist float32 [n_q, k], stats dict or None);
+    with stats, ``ms_ref_build``/``ms_query_build`` give the build times.
+    """
+    torch = _torch()
+    _dev_f32(ref_points, "ref_points")
+    if query_points is not None:
+        _dev_f32(query_points, "query_points")
+        if query_points.shape[1] != ref_points.shape[1]:
+            raise ValueError("ref_points and query_points differ in d")
+    nq = (query_points if query_points is not None else ref_points).shape[0]
+    if out is None:
+        idx = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+        dist = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+    else:
+        idx, dist = out
+    o, st = _make_opts(bound, precision, exclude_self, None, None, stats)
+    _check(load().knn_all_knn(ctypes.c_void_p(ref_points.data_ptr()), ref_points.shape[0],
+                              ctypes.c_void_p(query_points.data_ptr()) if query_points is not None
+                              else None, nq if query_points is not None else 0,
+                              ref_points.shape[1], int(leaf_size), int(k), ctypes.byref(o),
+                              ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(dist.data_ptr()),
+                              _stream(stream)))
     return idx, dist, _stats_dict(st)
 
 

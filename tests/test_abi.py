@@ -73,6 +73,24 @@ def test_build_tree_pair_rejects_bad_arguments(which):
     assert not ra.value and not qa.value
 
 
+@pytest.mark.parametrize("which", ["ref_null", "ref_n", "query_n", "bad_d", "bad_leaf"])
+def test_all_knn_rejects_bad_arguments(which):
+    # argument checks run before any device work (no GPU needed)
+    lib = knn.load()
+    o = knn.knn_opts()
+    lib.knn_opts_default(ctypes.byref(o))
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation comes first
+    ref = None if which == "ref_null" else fake
+    nr = 0 if which == "ref_n" else 10
+    nq = 0 if which == "query_n" else 10
+    d = 0 if which == "bad_d" else 3
+    leaf = 0 if which == "bad_leaf" else 8
+    st = lib.knn_all_knn(ref, nr, fake, nq, d, leaf, 3, ctypes.byref(o), ctypes.c_void_p(8),
+                         ctypes.c_void_p(8), None)
+    assert st == knn.KNN_E_INVALID_ARG
+    assert lib.knn_last_error()
+
+
 def test_search_rejects_null_tree():
     lib = knn.load()
     o = knn.knn_opts()

@@ -179,3 +179,64 @@ def test_bf16_low_dim_unsupported():
     with pytest.raises(knn.KnnError) as e:
         knn.knn_search(rt, None, 3, exclude_self=True, precision="bf16")
     assert e.value.status == knn.KNN_E_UNSUPPORTED
+
+
+# ---- the whole path in one call (knn_all_knn) --------------------------------
+def _all_knn(ref, q, k, leaf, precision="fp32", stats=False):
+    torch = _torch()
+    from paper_1304_4327_amd import knn
+    R = torch.from_numpy(ref).cuda()
+    Q = None if q is None else torch.from_numpy(q).cuda()
+    idx, dist, st = knn.knn_all_knn(R, Q, k, leaf, precision=precision, exclude_self=q is None,
+                                    stats=stats)
+    torch.cuda.synchronize()
+    return idx.cpu().numpy(), dist.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("name,scale", [("gmm1m_d3_k10", 0.03), ("manifold4m_d16_k10", 0.0075)])
+def test_all_knn_matches_oracle_and_separate_calls(name, scale):
+    """One call (both builds, search) equals the separate calls bit for bit
+    and passes the oracle check."""
+    ref, q, k, leaf = datagen.make(name, scale=scale)
+    gi, gd, st = _all_knn(ref, q, k, leaf, stats=True)
+    si, sd, _ = _search(ref, q, k, leaf)
+    np.testing.assert_array_equal(gi, si)
+    np.testing.assert_array_equal(gd, sd)
+    _check(ref, q, k, gi, gd)
+    assert st["ms_ref_build"] > 0 and st["ms_query_build"] > 0 and st["pairs"] > 0
+
+
+def test_all_knn_self_mode():
+    ref, _, k, leaf = datagen.make("uniform10k_d3_k5")
+    gi, gd, st = _all_knn(ref, None, k, leaf, stats=True)
+    si, sd, _ = _search(ref, None, k, leaf)
+    np.testing.assert_array_equal(gi, si)
+    np.testing.assert_array_equal(gd, sd)
+    _check(ref, None, k, gi, gd)
+    assert st["ms_query_build"] == 0
+
+
+def test_all_knn_bf16():
+    ref, q, k, leaf = datagen.make("manifold4m_d16_k10", scale=0.005)
+    gi, gd, _ = _all_knn(ref, q, k, leaf, precision="bf16")
+    _check(ref, q, k, gi, gd)
+
+
+@pytest.mark.parametrize("which", ["ref", "query"])
+def test_all_knn_nonfinite_rejected(which):
+    from paper_1304_4327_amd import knn
+    ref = datagen.uniform(6000, 3, seed=21)
+    qry = datagen.uniform(3000, 3, seed=22)
+    (ref if which == "ref" else qry)[77, 2] = np.nan
+    with pytest.raises(knn.KnnError) as e:
+        _all_knn(ref, qry, 4, 16)
+    assert e.value.status == knn.KNN_E_NONFINITE
+
+
+def test_all_knn_rejects_k_too_large():
+    from paper_1304_4327_amd import knn
+    ref = datagen.uniform(50, 3, seed=23)
+    qry = datagen.uniform(40, 3, seed=24)
+    with pytest.raises(knn.KnnError) as e:
+        _all_knn(ref, qry, 50, 8)
+    assert e.value.status == knn.KNN_E_INVALID_ARG
