@@ -252,18 +252,24 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
         }
         // survivors: one per lane per round, exact FP64 re-score, insert
         const float *qp = a.qpts + int64_t(qpos) * DP;
-        while (ballot(mask != 0)) {
+        // (unrolled: a loop here carried the lists and made the compiler
+        // copy them on every pass; a lane holds at most 16 survivors)
+#pragma unroll
+        for (int pass = 0; pass < 16; ++pass) {
+            if (!ballot(mask != 0)) break;
             ++n_pass;
-            if (mask) {
-                const int r = __builtin_ctz(mask);
-                mask &= mask - 1;
-                const int row = 8 * (r >> 2) + 4 * h + (r & 3);
-                const float x = (float)d2_fp64_rows<DP>(qp, a.rpts + int64_t(base + row) * DP);
-                if (x < dist[K - 1]) {
-                    insert(x, base + row);
-                    ++n_ins;
-                }
-            }
+            const bool has = mask != 0;
+            const int r = has ? __builtin_ctz(mask) : 0;
+            mask &= mask - 1;
+            const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+            float x = kInf;
+            if (has) x = (float)d2_fp64_rows<DP>(qp, a.rpts + int64_t(base + row) * DP);
+            // every lane runs the insert (a lane without a survivor inserts
+            // +inf, which moves nothing): a divergent insert made the
+            // compiler copy the whole list before it
+            const bool ins = has && x < dist[K - 1];
+            n_ins += ins;
+            insert(ins ? x : kInf, base + row);
         }
         refresh_bound();
     };
@@ -275,46 +281,55 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
         ++n_score;
         bool down = keep_of(score_box(a.rbox));
         if (down) {
+            // outer loop: one reference leaf per iteration; the inner walk
+            // leaves the k-lists untouched, so they are not carried through
+            // its loop (carried through one loop with the tile, the compiler
+            // moved every list register on every walk step)
             for (;;) {
-                if (down) {
-                    if (node >= a.r_first_leaf) {
-                        tile(node);
-                        down = false;
-                        continue;
-                    }
-                    const int c0 = 2 * node + 1, c1 = c0 + 1;
-                    n_score += 2;
-                    const float dm0 = score_box(a.rbox + int64_t(c0) * 2 * DP);
-                    const float dm1 = score_box(a.rbox + int64_t(c1) * 2 * DP);
-                    const bool k0 = keep_of(dm0), k1 = keep_of(dm1);
-                    if (!k0 && !k1) {
-                        down = false;
-                        continue;
-                    }
-                    const bool right = k1 && (!k0 || dm1 < dm0);
-                    if (right)
-                        nearbits |= (uint64_t(1) << depth);
-                    else
-                        nearbits &= ~(uint64_t(1) << depth);
-                    node = uniform_i(right ? c1 : c0);
-                    ++depth;
-                } else {
-                    if (node == 0) break;
-                    --depth;
-                    const bool is_right = (node & 1) == 0;
-                    const bool near_right = (nearbits >> depth) & 1;
-                    if (is_right == near_right) {
-                        const int far = is_right ? node - 1 : node + 1;
-                        ++n_score;
-                        if (keep_of(score_box(a.rbox + int64_t(far) * 2 * DP))) {
-                            node = far;
-                            ++depth;
-                            down = true;
+                bool leaf = false;
+                for (;;) {
+                    if (down) {
+                        if (node >= a.r_first_leaf) {
+                            leaf = true;
+                            break;
+                        }
+                        const int c0 = 2 * node + 1, c1 = c0 + 1;
+                        n_score += 2;
+                        const float dm0 = score_box(a.rbox + int64_t(c0) * 2 * DP);
+                        const float dm1 = score_box(a.rbox + int64_t(c1) * 2 * DP);
+                        const bool k0 = keep_of(dm0), k1 = keep_of(dm1);
+                        if (!k0 && !k1) {
+                            down = false;
                             continue;
                         }
+                        const bool right = k1 && (!k0 || dm1 < dm0);
+                        if (right)
+                            nearbits |= (uint64_t(1) << depth);
+                        else
+                            nearbits &= ~(uint64_t(1) << depth);
+                        node = uniform_i(right ? c1 : c0);
+                        ++depth;
+                    } else {
+                        if (node == 0) break;
+                        --depth;
+                        const bool is_right = (node & 1) == 0;
+                        const bool near_right = (nearbits >> depth) & 1;
+                        if (is_right == near_right) {
+                            const int far = is_right ? node - 1 : node + 1;
+                            ++n_score;
+                            if (keep_of(score_box(a.rbox + int64_t(far) * 2 * DP))) {
+                                node = far;
+                                ++depth;
+                                down = true;
+                                continue;
+                            }
+                        }
+                        node = uniform_i((node - 1) >> 1);
                     }
-                    node = uniform_i((node - 1) >> 1);
                 }
+                if (!leaf) break;
+                tile(node);
+                down = false;
             }
         }
     }

@@ -313,7 +313,10 @@ __global__ __launch_bounds__(256) void k_search_mfma_sweep(const SearchArgs a) {
         // The round body has no divergent branch: a lane without a survivor
         // re-scores row 0 and inserts +inf (a no-op); the wave issues the
         // same instructions either way.
-        for (;;) {
+        // (unrolled: a loop here carried the lists and made the compiler
+        // copy them on entry and exit; a lane holds at most 16 survivors)
+#pragma unroll
+        for (int pass = 0; pass < 16; ++pass) {
             const bool has = mask != 0;
             if (!ballot(has)) break;
             ++n_pass;
