@@ -40,7 +40,9 @@ PEAKS = {  # MI355X published dense peaks
 # counter reads for a plain 1 GiB device copy (--copy-calibration): FETCH_SIZE
 # x 2.000, WRITE_SIZE x 1.000.  Only workloads whose kernel is unchanged since
 # the counters were taken appear here.
-TRAFFIC_BYTES_PER_LAUNCH = {}
+TRAFFIC_BYTES_PER_LAUNCH = {
+    ("gmm1m_d3_k10", "fp32"): int((343185.5 * 2.000 + 159323.46875 * 1.000) * 1024),
+}
 
 
 def parse():
