@@ -97,9 +97,11 @@ def cpu_baseline(ref, q, k, self_mode, target_s):
         t0 = time.perf_counter()
         ok.knn_rows(qq, rows, ref, k, exclude_self=self_mode)
         elapsed = time.perf_counter() - t0
-        if elapsed >= target_s / 4 or n >= len(qq):
+        if elapsed >= 0.8 * target_s or n >= len(qq):
             break
-        n = int(min(len(qq), n * max(2.0, target_s / max(elapsed, 1e-3) * 0.9)))
+        # next sample sized for the target (growth capped, so a slow first
+        # estimate cannot overshoot far)
+        n = int(min(len(qq), n * min(16.0, max(1.5, target_s / max(elapsed, 1e-3) * 1.05))))
     return {"value": len(rows) / elapsed, "unit": "queries/s", "cores": ok.threads(),
             "kind": "oracle",
             "sample": f"{len(rows)} seeded queries x all {len(ref)} references "
