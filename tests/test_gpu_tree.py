@@ -125,6 +125,30 @@ def test_tree_pair_equals_separate_builds():
         assert np.array_equal(arr["hi"][live], o["hi"][live])
 
 
+@pytest.mark.parametrize("n,d,leaf", [(30000, 3, 16), (2000, 8, 8), (70000, 16, 32), (600, 3, 4)])
+def test_tree_pair_equal_sizes(n, d, leaf):
+    """Equal sizes, the two builds overlapped: every array equals a separate
+    build, bit for bit, and the oracle tree."""
+    import torch
+    from paper_1304_4327_amd import knn
+    ref = datagen.uniform(n, d, seed=31)
+    qry = datagen.gmm_pair(n, n, d, 8, seed=32)[1]
+    R, Q = torch.from_numpy(ref).cuda(), torch.from_numpy(qry).cuda()
+    ta, tb = knn.knn_build_tree_pair(R, Q, leaf)
+    pair = (knn.tree_arrays(ta), knn.tree_arrays(tb))
+    ta.close()
+    tb.close()
+    for pts, P in zip((ref, qry), pair):
+        t = knn.knn_build_tree(torch.from_numpy(pts).cuda(), leaf)
+        S = knn.tree_arrays(t)
+        t.close()
+        for key in ("points", "perm", "start", "count", "lo", "hi", "lam", "split_dim"):
+            live = S["count"] > 0 if key in ("lo", "hi", "lam") else slice(None)
+            np.testing.assert_array_equal(P[key][live], S[key][live], err_msg=key)
+        o = okd.build(pts, leaf)
+        assert np.array_equal(P["perm"], o["perm"])
+
+
 def test_tree_pair_nonfinite_rejected():
     import torch
     from paper_1304_4327_amd import knn
@@ -134,3 +158,11 @@ def test_tree_pair_nonfinite_rejected():
     with pytest.raises(knn.KnnError) as e:
         knn.knn_build_tree_pair(torch.from_numpy(ref).cuda(), torch.from_numpy(qry).cuda(), 8)
     assert e.value.status == knn.KNN_E_NONFINITE
+    # equal sizes, the bad value in either set
+    for which in (0, 1):
+        a = datagen.uniform(5000, 3, seed=15)
+        b = datagen.uniform(5000, 3, seed=16)
+        (a, b)[which][77, 2] = np.nan
+        with pytest.raises(knn.KnnError) as e:
+            knn.knn_build_tree_pair(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), 8)
+        assert e.value.status == knn.KNN_E_NONFINITE
