@@ -60,6 +60,8 @@ def parse():
                     help="train the seed network on 8 other seeded draws of the workload "
                          "(untimed), then time steps that include seed inference")
     ap.add_argument("--train-epochs", type=int, default=20)
+    ap.add_argument("--target-fallback", type=float, default=0.0005,
+                    help="seed calibration: share of held-out leaves allowed above the seed")
     ap.add_argument("--compare", action="store_true",
                     help="also time the plain FP32 path on the same workload and report "
                          "the speedup of the chosen variant over it")
@@ -141,8 +143,10 @@ def main():
             [base + 100 + i for i in range(8)]
         t0 = time.perf_counter()
         model = S.train_for_workload(args.workload, train_seeds, epochs=args.train_epochs,
-                                     precision=args.precision)
+                                     precision=args.precision,
+                                     target_fallback=args.target_fallback)
         train_info = {"train_seeds": train_seeds, "eval_seed": base,
+                      "target_fallback": args.target_fallback,
                       "train_s": time.perf_counter() - t0, "log_margin": model.log_margin,
                       "loss_first": model.history[0], "loss_last": model.history[-1]}
 

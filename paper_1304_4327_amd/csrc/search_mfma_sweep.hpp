@@ -50,8 +50,13 @@ struct SweepLds {
     static constexpr size_t bytes = off_misc + 16 * 4;
 };
 
+// Two workgroups per CU (two waves per SIMD) where the lists allow it: each
+// tile's latency chain (staging barrier, dependent MFMAs, LDS reads) is then
+// covered by the other workgroup.  For K <= 50 this fits 256 registers with a
+// few spills off the tile loop; larger lists keep one workgroup.
 template <int DP, int K>
-__global__ __launch_bounds__(256) void k_search_mfma_sweep(const SearchArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 50 ? 2 : 1))) void
+k_search_mfma_sweep(const SearchArgs a) {
     static_assert(DP % 16 == 0, "MFMA tiles need the stride to be a multiple of 16");
     using L = SweepLds<DP, K>;
     constexpr int S = DP / 16;  // k-steps of 16 dimensions
