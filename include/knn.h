@@ -83,7 +83,9 @@ typedef struct knn_stats {
     int64_t fallback_queries; /* queries whose k-th distance exceeded the seed   */
     float ms_query_build;     /* device time, query-tree build (0 if reused)     */
     float ms_search;          /* device time, traversal incl. fallback           */
-    float ms_main_kernel;     /* device time of the main traversal launch        */
+    float ms_main_kernel;     /* device time of the main traversal launch (FP32
+                                 with a seed: the second pass of the leaves
+                                 that missed their seed runs in this launch)    */
     int32_t n_query_leaves;   /* leaves of the query tree                        */
     int64_t fallback_pairs;   /* pairs evaluated by the fallback pass (included
                                  in `pairs`)                                     */

@@ -241,8 +241,11 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     KNN_HIP(hipEventRecord(ev[1], s));
     if (opts.seed_radius) {
         k_count_flags<<<(nq_leaves + 255) / 256, 256, 0, s>>>(fb_flag, nq_leaves, fb_count);
-        // fallback: the listed leaves again, from empty lists, with the
-        // proven bound of the first pass as their initial bound
+    }
+    if (opts.seed_radius && bf16) {
+        // fallback of the BF16 kernels: the listed leaves again, from empty
+        // lists, with the proven bound of the first pass as their initial
+        // bound (the FP32 kernel runs this second pass in the same wave)
         SearchArgs b = a;
         b.seed = fb_bound;
         b.fallback = nullptr;
@@ -250,7 +253,7 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
         b.active = fb_flag;
         b.stats = dstats ? dstats + ST_COUNT : nullptr;  // counted separately
         b.wave_log = nullptr;
-        KNN_HIP(bf16 ? launch_mfma(b, ref->dp, K, grid, s) : launch_valu(b, ref->d, K, grid, s));
+        KNN_HIP(launch_mfma(b, ref->dp, K, grid, s));
     }
     KNN_HIP(hipEventRecord(ev[2], s));
     unsigned long long hst[2 * ST_COUNT] = {};

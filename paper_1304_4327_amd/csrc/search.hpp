@@ -49,7 +49,9 @@ struct SearchArgs {
     float *fb_bound;    // per query leaf (seeded runs): a proven bound for the
                         // fallback pass, min D_p[k] + 2 lambda over the leaf's
                         // queries with a full list (+inf if none), or NULL
-    unsigned long long *stats;  // ST_COUNT counters, or NULL
+    unsigned long long *stats;  // ST_COUNT counters, or NULL; the FP32 kernel with a
+                                // seed adds its second pass's counts to the next
+                                // ST_COUNT
     uint32_t *wave_log;         // debug: 8 words per wave (ticks, scores, tiles, inserts, passes, leaf)
 };
 
@@ -64,6 +66,15 @@ hipError_t launch_search_valu_d8(const SearchArgs &a, int K, int grid, hipStream
 hipError_t launch_search_valu_d16(const SearchArgs &a, int K, int grid, hipStream_t s);
 hipError_t launch_search_valu_d32(const SearchArgs &a, int K, int grid, hipStream_t s);
 hipError_t launch_search_valu_d64(const SearchArgs &a, int K, int grid, hipStream_t s);
+// the same with a seed radius (search_seeded_d*.hip)
+hipError_t launch_search_valu_seeded_d1(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_valu_seeded_d2(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_valu_seeded_d3(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_valu_seeded_d4(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_valu_seeded_d8(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_valu_seeded_d16(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_valu_seeded_d32(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_valu_seeded_d64(const SearchArgs &a, int K, int grid, hipStream_t s);
 
 // BF16 MFMA kernels (search_mfma_d*.hip), stride 16, 32 or 64
 hipError_t launch_search_mfma_dp16(const SearchArgs &a, int K, int grid, hipStream_t s);

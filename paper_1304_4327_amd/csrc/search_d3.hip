@@ -1,8 +1,10 @@
-// Instantiation of the FP32 traversal kernel for 3 computed dimensions.
+// Instantiation of the FP32 traversal kernel for 3 computed dimensions
+// (searches without a seed; the seeded kernels are in search_seeded_d3.hip).
 #include "search_valu.hpp"
 
 namespace knnx {
 hipError_t launch_search_valu_d3(const SearchArgs &a, int K, int grid, hipStream_t s) {
-    return launch_search_valu<3>(a, K, grid, s);
+    if (a.seed) return launch_search_valu_seeded_d3(a, K, grid, s);
+    return launch_search_valu<3, false>(a, K, grid, s);
 }
 }  // namespace knnx
