@@ -5,6 +5,6 @@
 namespace knnx {
 hipError_t launch_search_valu_d32(const SearchArgs &a, int K, int grid, hipStream_t s) {
     if (a.seed) return launch_search_valu_seeded_d32(a, K, grid, s);
-    return launch_search_valu<32, false>(a, K, grid, s);
+    return launch_search_valu<32>(a, K, grid, s);
 }
 }  // namespace knnx

@@ -5,6 +5,6 @@
 namespace knnx {
 hipError_t launch_search_valu_d64(const SearchArgs &a, int K, int grid, hipStream_t s) {
     if (a.seed) return launch_search_valu_seeded_d64(a, K, grid, s);
-    return launch_search_valu<64, false>(a, K, grid, s);
+    return launch_search_valu<64>(a, K, grid, s);
 }
 }  // namespace knnx

@@ -5,6 +5,6 @@
 namespace knnx {
 hipError_t launch_search_valu_d8(const SearchArgs &a, int K, int grid, hipStream_t s) {
     if (a.seed) return launch_search_valu_seeded_d8(a, K, grid, s);
-    return launch_search_valu<8, false>(a, K, grid, s);
+    return launch_search_valu<8>(a, K, grid, s);
 }
 }  // namespace knnx

@@ -19,13 +19,14 @@
 //     slots per leaf, unused slots at FLT_MAX so their distance is +inf);
 //   * the k-list is a sorted register array of K slots; for k < K the first
 //     K-k slots hold -inf and never move, so the k-th value is always slot
-//     K-1 (the list is "ordered by ascending distance", Algorithm 2);
+//     K-1 (Algorithm 2 keeps each list sorted by distance);
 //   * after each tile the leaf bound is refreshed:
 //        B1 = max over the leaf's queries of D_p[k]              (B1(N_q))
 //        B2 = min over the leaf's queries of D_p[k] + 2 lambda    (rho = lambda)
 //        BP = min over the queries of an ancestor + 2 lambda(anc) (B(Par))
-//        B  = min(B1, B2, BP, seed)
-//     and a node is pruned when d_min^2 > B^2 (1 + 2^-16).
+//        B  = min(B1, B2, BP)
+//     (the seeded kernel in search_valu_seeded.hpp adds the seed radius to
+//     the min) and a node is pruned when d_min^2 > B^2 (1 + 2^-16).
 //   * all-kNN of a set on itself keeps k+1 entries per list; the query's own
 //     point (distance 0) takes one of them and is dropped at write-out, so no
 //     per-pair index test is needed.
@@ -70,7 +71,7 @@ __device__ inline double d2_fp64(const float (&q)[D], const float *r) {
     return s;
 }
 
-template <int D, int K, int LG, bool SEEDED>
+template <int D, int K, int LG>
 __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     constexpr int DP = stride_for(D);
     constexpr bool RESCORE = D > 8;
@@ -98,8 +99,7 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     const int qleaf = has_leaf ? slot : 0;
     const int qnode = a.q_first_leaf + qleaf;
     const int2 qr = has_leaf ? a.qrange[qnode] : make_int2(0, 0);
-    const bool valid0 = has_leaf && li < qr.y;  // this lane holds a query point
-    bool valid = valid0;  // ... that the current pass searches
+    const bool valid = has_leaf && li < qr.y;
     const int qpos = qr.x + li;
     const int kk = a.k + (a.self ? 1 : 0);  // list length (self match included)
 
@@ -143,10 +143,6 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         uhi[0] = hi;
     }
     const float lam2 = has_leaf ? 2.0f * a.qlam[qnode] : 0.f;
-    // a seed is only a pruning radius; NaN or negative values prune
-    // everything and send the leaf to the fallback pass
-    const float seed = (a.seed && has_leaf) ? fmaxf(a.seed[qleaf], 0.0f) : kInf;
-    float seed2 = seed * seed;
 
     float dist[K];
     int idx[K];
@@ -155,10 +151,10 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         dist[j] = (j < K - kk) ? -kInf : kInf;
         idx[j] = -1;
     }
-    float bound2 = (a.bound == KNN_BOUND_NONE) ? kInf : seed2;
+    float bound2 = kInf;
     uint32_t n_score = 0, n_tiles = 0, n_ins = 0, n_pass = 0;
     uint64_t n_pairs = 0;
-    int n_valid = __popcll(ballot(valid));
+    const int n_valid = __popcll(ballot(valid));
 
     // Prefetch into the scalar cache: a few scalar loads of lines that the
     // next steps will read, issued together with loads that are waited for
@@ -285,7 +281,7 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
                 }
             }
         }
-        bound2 = fminf(b, seed2);
+        bound2 = b;
     };
 
     // BaseCase over one reference leaf: every lane against each reference
@@ -358,18 +354,6 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     };
 
     // ---- stackless depth-first walk, nearer child first ---------------------
-    // With a seed, a second pass follows in the same wave: leaves with a query
-    // whose k-th distance exceeds its seed are searched again from empty
-    // lists, with the proven B2 bound of the first pass as initial bound and
-    // no seed; the other leaf's lanes sit out (their lists are final).  The
-    // second pass of a few leaves then runs beside the other waves instead of
-    // as a launch of its own.
-    uint32_t s_score = 0, s_tiles = 0;  // first-pass counts
-    uint64_t s_pairs = 0;
-    int s_ins = 0;
-    bool fb_q = false, fb_leaf = false;  // this lane's query / leaf missed its seed
-    bool second = false;                 // a second pass ran in this wave
-    auto walk = [&]() {
     {
         float dm0, dm1;
         int node = 0, depth = 0;
@@ -425,42 +409,6 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
             }
         }
     }
-    };
-    walk();
-    // (a separate instantiation: the second walk costs registers that the
-    // unseeded kernel need not hold)
-    if constexpr (SEEDED) {
-        // seed check on the list (FP32 squared distances: their error is far
-        // inside the check's factor)
-        fb_q = valid && !(dist[K - 1] <= seed2 * (1.0f - 0x1p-18f));
-        if (ballot(fb_q)) {
-            float f = fb_q ? 1.0f : 0.0f;
-            for (int l = 0; l < lpl_log2; ++l) f = xor_level(f, l, OpMax());
-            fb_leaf = valid && f > 0.0f;
-            // proven bound for the leaf: min over its full lists of D_p[k]
-            // plus 2 lambda (the B2 argument holds whatever seed built the
-            // lists)
-            float kb = (valid && dist[K - 1] < kInf) ? __builtin_amdgcn_sqrtf(dist[K - 1]) : kInf;
-            for (int l = 0; l < lpl_log2; ++l) kb = xor_level(kb, l, OpMin());
-            const float pb = (kb + lam2) * (1.0f + 0x1p-18f);
-            second = true;
-            s_score = n_score;
-            s_tiles = n_tiles;
-            s_pairs = n_pairs;
-            s_ins = n_ins;
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-                dist[j] = fb_leaf ? ((j < K - kk) ? -kInf : kInf) : dist[j];
-                idx[j] = fb_leaf ? -1 : idx[j];
-            }
-            valid = fb_leaf;
-            n_valid = __popcll(ballot(valid));
-            seed2 = kInf;
-            bound2 = (a.bound == KNN_BOUND_NONE || !fb_leaf) ? kInf : pb * pb;
-            walk();
-        }
-    }
-    valid = valid0;
 
     // keeps the prefetch loads (k >= 1 always)
     if ((tacc ^ q0 ^ q1 ^ q2) == 0x7fc00001u && a.k < 0) a.out_idx[0] = 0;
@@ -492,21 +440,13 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
             }
         }
     }
-    // largest k-th distance of the leaf; leaves searched a second time are
-    // flagged (counted by the host)
+    // largest k-th distance of the leaf
     for (int l = 0; l < lpl_log2; ++l) worst = xor_level(worst, l, OpMax());
-    const uint64_t fbmask = ballot(fb_q);
-    if (has_leaf && li == 0) {
-        if (a.leaf_kth) a.leaf_kth[qleaf] = fmaxf(worst, 0.0f);
-        if (a.fallback && fb_leaf) a.fallback[qleaf] = 1;
-    }
+    if (has_leaf && li == 0 && a.leaf_kth) a.leaf_kth[qleaf] = fmaxf(worst, 0.0f);
     if (a.wave_log || a.stats) {
-        int ins = n_ins, ins1 = second ? s_ins : n_ins;
+        int ins = n_ins;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            ins += __shfl_xor(ins, off);
-            ins1 += __shfl_xor(ins1, off);
-        }
+        for (int off = 32; off > 0; off >>= 1) ins += __shfl_xor(ins, off);
         if (a.wave_log && lane == 0) {
             uint32_t *w = a.wave_log + int64_t(wave) * 8;
             w[0] = 0;  // no clock read: a side-effecting read here would
@@ -518,50 +458,39 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
             w[5] = uint32_t(qleaf);
         }
         if (a.stats && lane == 0) {
-            // first-pass counts, then the second pass's in the fallback block
-            const uint32_t sc1 = second ? s_score : n_score, ti1 = second ? s_tiles : n_tiles;
-            const uint64_t pa1 = second ? s_pairs : n_pairs;
-            atomicAdd(&a.stats[ST_SCORE], (unsigned long long)sc1);
-            atomicAdd(&a.stats[ST_TILES], (unsigned long long)ti1);
-            atomicAdd(&a.stats[ST_PAIRS], (unsigned long long)pa1);
-            atomicAdd(&a.stats[ST_INSERTS], (unsigned long long)ins1);
-            atomicAdd(&a.stats[ST_FB_QUERIES], (unsigned long long)__popcll(fbmask));
-            if (second) {
-                unsigned long long *f = a.stats + ST_COUNT;
-                atomicAdd(&f[ST_SCORE], (unsigned long long)(n_score - sc1));
-                atomicAdd(&f[ST_TILES], (unsigned long long)(n_tiles - ti1));
-                atomicAdd(&f[ST_PAIRS], (unsigned long long)(n_pairs - pa1));
-                atomicAdd(&f[ST_INSERTS], (unsigned long long)(ins - ins1));
-            }
+            atomicAdd(&a.stats[ST_SCORE], (unsigned long long)n_score);
+            atomicAdd(&a.stats[ST_TILES], (unsigned long long)n_tiles);
+            atomicAdd(&a.stats[ST_PAIRS], (unsigned long long)n_pairs);
+            atomicAdd(&a.stats[ST_INSERTS], (unsigned long long)ins);
         }
     }
 }
 
-template <int D, int K, bool SEEDED>
-hipError_t launch_search_valu_ks(const SearchArgs &a, int grid, hipStream_t s) {
+template <int D, int K>
+hipError_t launch_search_valu_k(const SearchArgs &a, int grid, hipStream_t s) {
     switch (a.lpl_log2) {
-        case 3: k_search_valu<D, K, 3, SEEDED><<<grid, 256, 0, s>>>(a); break;
-        case 4: k_search_valu<D, K, 4, SEEDED><<<grid, 256, 0, s>>>(a); break;
-        case 5: k_search_valu<D, K, 5, SEEDED><<<grid, 256, 0, s>>>(a); break;
-        case 6: k_search_valu<D, K, 6, SEEDED><<<grid, 256, 0, s>>>(a); break;
+        case 3: k_search_valu<D, K, 3><<<grid, 256, 0, s>>>(a); break;
+        case 4: k_search_valu<D, K, 4><<<grid, 256, 0, s>>>(a); break;
+        case 5: k_search_valu<D, K, 5><<<grid, 256, 0, s>>>(a); break;
+        case 6: k_search_valu<D, K, 6><<<grid, 256, 0, s>>>(a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int D, bool SEEDED>
+template <int D>
 hipError_t launch_search_valu(const SearchArgs &a, int K, int grid, hipStream_t s) {
     switch (K) {
-        case 4: return launch_search_valu_ks<D, 4, SEEDED>(a, grid, s);
-        case 5: return launch_search_valu_ks<D, 5, SEEDED>(a, grid, s);
-        case 8: return launch_search_valu_ks<D, 8, SEEDED>(a, grid, s);
-        case 10: return launch_search_valu_ks<D, 10, SEEDED>(a, grid, s);
-        case 11: return launch_search_valu_ks<D, 11, SEEDED>(a, grid, s);
-        case 16: return launch_search_valu_ks<D, 16, SEEDED>(a, grid, s);
-        case 32: return launch_search_valu_ks<D, 32, SEEDED>(a, grid, s);
-        case 50: return launch_search_valu_ks<D, 50, SEEDED>(a, grid, s);
-        case 51: return launch_search_valu_ks<D, 51, SEEDED>(a, grid, s);
-        case 64: return launch_search_valu_ks<D, 64, SEEDED>(a, grid, s);
+        case 4: return launch_search_valu_k<D, 4>(a, grid, s);
+        case 5: return launch_search_valu_k<D, 5>(a, grid, s);
+        case 8: return launch_search_valu_k<D, 8>(a, grid, s);
+        case 10: return launch_search_valu_k<D, 10>(a, grid, s);
+        case 11: return launch_search_valu_k<D, 11>(a, grid, s);
+        case 16: return launch_search_valu_k<D, 16>(a, grid, s);
+        case 32: return launch_search_valu_k<D, 32>(a, grid, s);
+        case 50: return launch_search_valu_k<D, 50>(a, grid, s);
+        case 51: return launch_search_valu_k<D, 51>(a, grid, s);
+        case 64: return launch_search_valu_k<D, 64>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

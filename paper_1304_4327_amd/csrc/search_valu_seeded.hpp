@@ -1,0 +1,509 @@
+// FP32 traversal kernel for searches with a seed radius.  A seed (not in the
+// paper) is only an initial value of a query leaf's pruning bound; a leaf
+// whose k-th distances exceed it is searched again without it.  Traversal,
+// Score (Algorithm 3) and BaseCase (Algorithm 2) are those of the unseeded
+// kernel in search_valu.hpp; this kernel adds the seed to the leaf bound and
+// runs the second pass of the leaves that missed it inside the same wave,
+// from empty lists, with the proven bound of the first pass.  It is a kernel
+// of its own so that the unseeded kernel carries none of its state.
+#pragma once
+
+#include "search_valu.hpp"
+
+namespace knnx {
+
+template <int D, int K, int LG>
+__global__ __launch_bounds__(256) void k_search_valu_seeded(const SearchArgs a) {
+    constexpr int DP = stride_for(D);
+    constexpr bool RESCORE = D > 8;
+    constexpr float kInf = __builtin_inff();
+    constexpr float kSlack = 1.0f + 0x1p-16f;            // prune slack (squared)
+    constexpr float kGamma = 1.0f + (D + 6) * 0x1p-24f;  // FP32 filter slack
+    const int lane = threadIdx.x & 63;
+    constexpr int lpl_log2 = LG;
+    constexpr int NG = 64 >> lpl_log2;
+    const int n_list = a.q_n_leaves;
+    int wave;
+    if (a.order) {
+        // heavy slots first: the hardware starts workgroups in launch order
+        const int raw = blockIdx.x * 4 + (threadIdx.x >> 6);
+        if (raw * NG >= n_list) return;
+        wave = uniform_i(a.order[raw]);
+    } else {
+        wave = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    }
+    if (wave * NG >= n_list) return;
+    const int g = lane >> lpl_log2, li = lane & ((1 << lpl_log2) - 1);
+    const int slot = wave * NG + g;
+    const bool has_leaf = slot < n_list && (!a.active || a.active[slot] != 0);
+    if (!ballot(has_leaf)) return;
+    const int qleaf = has_leaf ? slot : 0;
+    const int qnode = a.q_first_leaf + qleaf;
+    const int2 qr = has_leaf ? a.qrange[qnode] : make_int2(0, 0);
+    const bool valid0 = has_leaf && li < qr.y;  // this lane holds a query point
+    bool valid = valid0;  // ... that the current pass searches
+    const int qpos = qr.x + li;
+    const int kk = a.k + (a.self ? 1 : 0);  // list length (self match included)
+
+    float q[D];
+    {
+        const float *qp = a.qpts + int64_t(valid ? qpos : 0) * DP;
+#pragma unroll
+        for (int j = 0; j < D; ++j) q[j] = valid ? qp[j] : 0.f;
+    }
+    // union box of the wave's query leaves, for the wave-uniform visit-order
+    // key.  Low d: every lane holds the whole box.  High d: lane l holds
+    // dimension l of it (the key is then summed across lanes).
+    constexpr bool WIDE = D >= 16;
+    constexpr int UD = WIDE ? 1 : D;
+    float ulo[UD], uhi[UD];
+    if constexpr (!WIDE) {
+        const float *qb = a.qbox + int64_t(has_leaf ? qnode : 0) * 2 * DP;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            float lo = has_leaf ? qb[j] : kInf;
+            float hi = has_leaf ? qb[DP + j] : -kInf;
+#pragma unroll
+            for (int l = lpl_log2; l < 6; ++l) {
+                lo = xor_level(lo, l, OpMin());
+                hi = xor_level(hi, l, OpMax());
+            }
+            ulo[j] = lo;
+            uhi[j] = hi;
+        }
+    } else {
+        float lo = lane < DP ? kInf : 0.f, hi = lane < DP ? -kInf : 0.f;
+        for (int gg = 0; gg < NG; ++gg) {
+            const int sl = wave * NG + gg;
+            if (sl < n_list && (!a.active || a.active[sl] != 0) && lane < DP) {
+                const float *qb = a.qbox + int64_t(a.q_first_leaf + sl) * 2 * DP;
+                lo = fminf(lo, qb[lane]);
+                hi = fmaxf(hi, qb[DP + lane]);
+            }
+        }
+        ulo[0] = lo;
+        uhi[0] = hi;
+    }
+    const float lam2 = has_leaf ? 2.0f * a.qlam[qnode] : 0.f;
+    // a seed is only a pruning radius; NaN or negative values prune
+    // everything and send the leaf to the fallback pass
+    const float seed = (a.seed && has_leaf) ? fmaxf(a.seed[qleaf], 0.0f) : kInf;
+    float seed2 = seed * seed;
+
+    float dist[K];
+    int idx[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        dist[j] = (j < K - kk) ? -kInf : kInf;
+        idx[j] = -1;
+    }
+    float bound2 = (a.bound == KNN_BOUND_NONE) ? kInf : seed2;
+    uint32_t n_score = 0, n_tiles = 0, n_ins = 0, n_pass = 0;
+    uint64_t n_pairs = 0;
+    int n_valid = __popcll(ballot(valid));
+
+    // Prefetch into the scalar cache: a few scalar loads of lines that the
+    // next steps will read, issued together with loads that are waited for
+    // anyway.  Their values are folded into tacc one step later (a use at
+    // once would make the wave wait for them) and reach a store that never
+    // happens, so the compiler keeps them.
+    uint32_t tacc = 0, q0 = 0, q1 = 0, q2 = 0;
+    // per-point bound: min(D_p[k], B(leaf)); +inf without pruning
+    auto point_bound2 = [&]() -> float {
+        return a.bound == KNN_BOUND_NONE ? kInf : fminf(bound2, dist[K - 1]);
+    };
+
+    // Score a reference node from its box: keep when any point's d_min^2 to
+    // the box is within its bound; the visit-order key is the wave-uniform
+    // d_min^2 between the union of the wave's leaf boxes and the node's box
+    auto score_box = [&](const float *b, float &key_out) -> bool {
+        float sd = 0.f, u = 0.f;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const float lo = b[j], hi = b[DP + j];
+            const float gap = fmaxf(fmaxf(lo - q[j], q[j] - hi), 0.0f);
+            sd = fmaf(gap, gap, sd);
+            if constexpr (!WIDE) {
+                const float ug = fmaxf(fmaxf(lo - uhi[j], ulo[j] - hi), 0.0f);
+                u = fmaf(ug, ug, u);
+            }
+        }
+        if constexpr (WIDE) {
+            const float lo = lane < DP ? b[lane] : 0.f, hi = lane < DP ? b[DP + lane] : 0.f;
+            const float ug = fmaxf(fmaxf(lo - uhi[0], ulo[0] - hi), 0.0f);
+            u = ug * ug;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off);
+        }
+        const bool keep = valid && !(sd > point_bound2() * kSlack);
+        key_out = uniform_f(u);
+        return ballot(keep) != 0;
+    };
+    auto score = [&](int node, float &key_out) -> bool {
+        ++n_score;
+        return score_box(a.rbox + int64_t(node) * 2 * DP, key_out);
+    };
+    // both children of an internal node: their boxes are adjacent
+    auto score_children = [&](int c0, bool &k0, bool &k1, float &m0, float &m1) {
+        n_score += 2;
+        const float *b = a.rbox + int64_t(c0) * 2 * DP;
+        // prefetch, issued with the children's box loads: the four
+        // grandchildren's boxes (contiguous), or the first lines of both
+        // leaves' tiles
+        uint32_t p0 = 0, p1 = 0, p2 = 0;
+        if constexpr (DP <= 4) {
+            const bool inner = c0 < a.r_first_leaf;
+            const float *g = inner ? a.rbox + int64_t(2 * c0 + 1) * 2 * DP
+                                   : a.rlpts + int64_t(c0 - a.r_first_leaf) * a.r_leaf_slots * DP;
+            const int s1 = inner ? 16 : a.r_leaf_slots * DP;
+            const int s2 = inner ? 8 * DP - 1 : a.r_leaf_slots * DP + 16;
+            p0 = __float_as_uint(g[0]);
+            p1 = __float_as_uint(g[s1]);
+            p2 = __float_as_uint(g[s2]);
+        }
+        k0 = score_box(b, m0);
+        k1 = score_box(b + 2 * DP, m1);
+        tacc ^= q0 ^ q1 ^ q2;
+        q0 = p0;
+        q1 = p1;
+        q2 = p2;
+    };
+
+    auto insert = [&](float x, int id) {
+#pragma unroll
+        for (int j = K - 1; j >= 0; --j) {
+            const float dj = dist[j];
+            const float dprev = (j > 0) ? dist[j - 1] : -kInf;
+            const int iprev = (j > 0) ? idx[j - 1] : -1;
+            const bool cprev = x < dprev;
+            const bool cj = x < dj;
+            dist[j] = cprev ? dprev : (cj ? x : dj);
+            idx[j] = cprev ? iprev : (cj ? id : idx[j]);
+        }
+    };
+
+    // B(Par(N_q)) terms: the ancestors whose leaves all sit in this wave
+    // (aligned sibling groups) contribute min D_p[k] + 2 lambda(ancestor)
+    // from the live lists; ancestors reaching outside the wave are left out
+    // of the minimum, which only loosens it.
+    const bool par_ok = a.bound == KNN_BOUND_B;
+    float lam2_anc[6];
+#pragma unroll
+    for (int s = 1; s <= 5; ++s) {
+        // no such ancestor (shallow tree): the term is +inf
+        lam2_anc[s] = kInf;
+        if (par_ok && ((1 << lpl_log2) << (s - 1)) < 64 && has_leaf && ((qnode + 1) >> s) >= 1)
+            lam2_anc[s] = 2.0f * a.qlam[((qnode + 1) >> s) - 1];
+    }
+    lam2_anc[0] = lam2;
+
+    // refresh of B(N_q) after a tile.  The group reductions step through
+    // the lane levels 0 .. lpl_log2-1 (uniform branches: DPP inside a row,
+    // a shuffle across rows); the B(Par) terms continue one level per
+    // ancestor.  The square root is the hardware one (about 1 ulp): its
+    // error is far inside the prune slack.
+    auto refresh_bound = [&]() {
+        if (a.bound == KNN_BOUND_NONE) return;
+        float hi = valid ? dist[K - 1] : -kInf;
+        float lo = valid ? dist[K - 1] : kInf;
+#pragma unroll
+        for (int l = 0; l < lpl_log2; ++l) {
+            hi = xor_level(hi, l, OpMax());
+            lo = xor_level(lo, l, OpMin());
+        }
+        float b = hi;  // B1^2
+        if (a.bound == KNN_BOUND_B) {
+            const float b2 = __builtin_amdgcn_sqrtf(lo) + lam2;
+            b = fminf(b, b2 * b2);
+            if (par_ok) {
+#pragma unroll
+                for (int s = 1; s <= 5; ++s) {
+                    const int l = lpl_log2 + s - 1;
+                    if (l < 6) {
+                        lo = xor_level(lo, l, OpMin());
+                        const float bp = __builtin_amdgcn_sqrtf(lo) + lam2_anc[s];
+                        b = fminf(b, bp * bp);
+                    }
+                }
+            }
+        }
+        bound2 = fminf(b, seed2);
+    };
+
+    // BaseCase over one reference leaf: every lane against each reference
+    // point, CH points per batch.  A candidate must beat min(D_p[k], B):
+    // B bounds the point's final k-th distance, so anything farther cannot
+    // enter its final list (equal distances aside).
+    // BaseCase over one reference leaf: every lane against each reference
+    // point, CH points per batch.  A candidate must beat min(D_p[k], B):
+    // B bounds the point's final k-th distance, so anything farther cannot
+    // enter its final list (equal distances aside).
+    constexpr int CH = DP >= 32 ? 1 : 32 / DP;
+    auto tile = [&](int node) {
+        ++n_tiles;
+        const int2 rr = a.rrange[node];
+        const int base = uniform_i(rr.x);
+        const int cnt = uniform_i(rr.y);
+        const float *rp = a.rlpts + int64_t(node - a.r_first_leaf) * a.r_leaf_slots * DP;
+        n_pairs += uint64_t(cnt) * uint64_t(n_valid);
+        const float bnd = bound2 * kSlack;
+        uint32_t r0 = 0, r1 = 0, r2 = 0;
+        if constexpr (DP <= 4) {
+            // the tile's later 64-byte lines, fetched with the first batch
+            const int last = max(cnt * DP - 1, 0);
+            r0 = __float_as_uint(rp[min(32, last)]);
+            r1 = __float_as_uint(rp[min(64, last)]);
+            r2 = __float_as_uint(rp[min(96, last)]);
+        }
+        for (int t0 = 0; t0 < cnt; t0 += CH) {
+            float sd[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                float acc = 0.f;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const float df = q[j] - rp[(t0 + c) * DP + j];
+                    acc = fmaf(df, df, acc);
+                }
+                sd[c] = acc;
+            }
+            // one wave-wide test per batch: most batches hold no candidate
+            // for any lane once the lists have filled
+            // (invalid lanes test against -inf; a plain compare ballots
+            // straight into a lane mask)
+            const float lim0 = fminf(dist[K - 1], bnd);
+            const float thr0 = valid ? (RESCORE ? lim0 * kGamma : lim0) : -kInf;
+            uint64_t any = 0;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) any |= ballot(sd[c] < thr0);
+            if (any == 0) continue;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const float lim = fminf(dist[K - 1], bnd);
+                const float thr = RESCORE ? lim * kGamma : lim;
+                const bool cand = valid && sd[c] < thr;
+                if (ballot(cand)) {
+                    ++n_pass;
+                    if (cand) {
+                        float x = sd[c];
+                        if (RESCORE) x = (float)d2_fp64<D>(q, rp + (t0 + c) * DP);
+                        if (x < dist[K - 1]) {
+                            insert(x, base + t0 + c);
+                            ++n_ins;
+                        }
+                    }
+                }
+            }
+        }
+        tacc ^= r0 ^ r1 ^ r2;
+        refresh_bound();
+    };
+
+    // ---- stackless depth-first walk, nearer child first ---------------------
+    // With a seed, a second pass follows in the same wave: leaves with a query
+    // whose k-th distance exceeds its seed are searched again from empty
+    // lists, with the proven B2 bound of the first pass as initial bound and
+    // no seed; the other leaf's lanes sit out (their lists are final).  The
+    // second pass of a few leaves then runs beside the other waves instead of
+    // as a launch of its own.
+    uint32_t s_score = 0, s_tiles = 0;  // first-pass counts
+    uint64_t s_pairs = 0;
+    int s_ins = 0;
+    bool fb_q = false, fb_leaf = false;  // this lane's query / leaf missed its seed
+    bool second = false;                 // a second pass ran in this wave
+    auto walk = [&]() {
+    {
+        float dm0, dm1;
+        int node = 0, depth = 0;
+        uint64_t nearbits = 0;
+        bool down = score(0, dm0);
+        if (down) {
+            // outer loop: one reference leaf per iteration; the inner walk
+            // leaves the k-lists untouched, so they are not carried through
+            // its loop (carried through one loop with the tile, the compiler
+            // moved every list register on every walk step)
+            for (;;) {
+                bool leaf = false;
+                for (;;) {
+                    if (down) {
+                        if (node >= a.r_first_leaf) {
+                            leaf = true;
+                            break;
+                        }
+                        const int c0 = 2 * node + 1, c1 = c0 + 1;
+                        bool k0, k1;
+                        score_children(c0, k0, k1, dm0, dm1);
+                        if (!k0 && !k1) {
+                            down = false;
+                            continue;
+                        }
+                        const bool right = k1 && (!k0 || dm1 < dm0);
+                        if (right)
+                            nearbits |= (uint64_t(1) << depth);
+                        else
+                            nearbits &= ~(uint64_t(1) << depth);
+                        node = uniform_i(right ? c1 : c0);
+                        ++depth;
+                    } else {
+                        if (node == 0) break;
+                        --depth;
+                        const bool is_right = (node & 1) == 0;
+                        const bool near_right = (nearbits >> depth) & 1;
+                        if (is_right == near_right) {
+                            const int far = is_right ? node - 1 : node + 1;
+                            if (score(far, dm0)) {
+                                node = far;
+                                ++depth;
+                                down = true;
+                                continue;
+                            }
+                        }
+                        node = uniform_i((node - 1) >> 1);
+                    }
+                }
+                if (!leaf) break;
+                tile(node);
+                down = false;
+            }
+        }
+    }
+    };
+    walk();
+    {
+        // seed check on the list (FP32 squared distances: their error is far
+        // inside the check's factor)
+        fb_q = valid && !(dist[K - 1] <= seed2 * (1.0f - 0x1p-18f));
+        if (ballot(fb_q)) {
+            float f = fb_q ? 1.0f : 0.0f;
+            for (int l = 0; l < lpl_log2; ++l) f = xor_level(f, l, OpMax());
+            fb_leaf = valid && f > 0.0f;
+            // proven bound for the leaf: min over its full lists of D_p[k]
+            // plus 2 lambda (the B2 argument holds whatever seed built the
+            // lists)
+            float kb = (valid && dist[K - 1] < kInf) ? __builtin_amdgcn_sqrtf(dist[K - 1]) : kInf;
+            for (int l = 0; l < lpl_log2; ++l) kb = xor_level(kb, l, OpMin());
+            const float pb = (kb + lam2) * (1.0f + 0x1p-18f);
+            second = true;
+            s_score = n_score;
+            s_tiles = n_tiles;
+            s_pairs = n_pairs;
+            s_ins = n_ins;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                dist[j] = fb_leaf ? ((j < K - kk) ? -kInf : kInf) : dist[j];
+                idx[j] = fb_leaf ? -1 : idx[j];
+            }
+            valid = fb_leaf;
+            n_valid = __popcll(ballot(valid));
+            seed2 = kInf;
+            bound2 = (a.bound == KNN_BOUND_NONE || !fb_leaf) ? kInf : pb * pb;
+            walk();
+        }
+    }
+    valid = valid0;
+
+    // keeps the prefetch loads (k >= 1 always)
+    if ((tacc ^ q0 ^ q1 ^ q2) == 0x7fc00001u && a.k < 0) a.out_idx[0] = 0;
+    // ---- write-out: FP64 re-score of the final list, order by (d, index) ----
+    // Each entry becomes its output key in place: the FP32 distance from the
+    // FP64 re-score and the original index.  Padding slots (below K-kk),
+    // unfilled slots and the query's own point get distinct +inf keys that
+    // rank after every real entry, so real entries take ranks 0..k-1.
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const bool real = valid && idx[j] >= 0 && !(a.self && idx[j] == qpos);
+        const int p = real ? idx[j] : 0;
+        dist[j] = real ? (float)sqrt(d2_fp64<D>(q, a.rpts + int64_t(p) * DP)) : kInf;
+        idx[j] = real ? a.rperm[p] : 0x7fffffff - j;
+    }
+    float worst = -1.0f;
+    if (valid) {
+        const int64_t row = int64_t(a.qperm[qpos]) * a.k;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            int rank = 0;
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                rank += (dist[i] < dist[j]) || (dist[i] == dist[j] && idx[i] < idx[j]);
+            if (rank < a.k) {
+                a.out_idx[row + rank] = idx[j] >= 0x7fffffff - K ? -1 : idx[j];
+                a.out_dist[row + rank] = dist[j];
+                if (rank == a.k - 1) worst = dist[j];
+            }
+        }
+    }
+    // largest k-th distance of the leaf; leaves searched a second time are
+    // flagged (counted by the host)
+    for (int l = 0; l < lpl_log2; ++l) worst = xor_level(worst, l, OpMax());
+    const uint64_t fbmask = ballot(fb_q);
+    if (has_leaf && li == 0) {
+        if (a.leaf_kth) a.leaf_kth[qleaf] = fmaxf(worst, 0.0f);
+        if (a.fallback && fb_leaf) a.fallback[qleaf] = 1;
+    }
+    if (a.wave_log || a.stats) {
+        int ins = n_ins, ins1 = second ? s_ins : n_ins;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            ins += __shfl_xor(ins, off);
+            ins1 += __shfl_xor(ins1, off);
+        }
+        if (a.wave_log && lane == 0) {
+            uint32_t *w = a.wave_log + int64_t(wave) * 8;
+            w[0] = 0;  // no clock read: a side-effecting read here would
+                       // turn every uniform load above into a vector load
+            w[1] = n_score;
+            w[2] = n_tiles;
+            w[3] = uint32_t(ins);
+            w[4] = n_pass;
+            w[5] = uint32_t(qleaf);
+        }
+        if (a.stats && lane == 0) {
+            // first-pass counts, then the second pass's in the fallback block
+            const uint32_t sc1 = second ? s_score : n_score, ti1 = second ? s_tiles : n_tiles;
+            const uint64_t pa1 = second ? s_pairs : n_pairs;
+            atomicAdd(&a.stats[ST_SCORE], (unsigned long long)sc1);
+            atomicAdd(&a.stats[ST_TILES], (unsigned long long)ti1);
+            atomicAdd(&a.stats[ST_PAIRS], (unsigned long long)pa1);
+            atomicAdd(&a.stats[ST_INSERTS], (unsigned long long)ins1);
+            atomicAdd(&a.stats[ST_FB_QUERIES], (unsigned long long)__popcll(fbmask));
+            if (second) {
+                unsigned long long *f = a.stats + ST_COUNT;
+                atomicAdd(&f[ST_SCORE], (unsigned long long)(n_score - sc1));
+                atomicAdd(&f[ST_TILES], (unsigned long long)(n_tiles - ti1));
+                atomicAdd(&f[ST_PAIRS], (unsigned long long)(n_pairs - pa1));
+                atomicAdd(&f[ST_INSERTS], (unsigned long long)(ins - ins1));
+            }
+        }
+    }
+}
+
+template <int D, int K>
+hipError_t launch_search_valu_seeded_k(const SearchArgs &a, int grid, hipStream_t s) {
+    switch (a.lpl_log2) {
+        case 3: k_search_valu_seeded<D, K, 3><<<grid, 256, 0, s>>>(a); break;
+        case 4: k_search_valu_seeded<D, K, 4><<<grid, 256, 0, s>>>(a); break;
+        case 5: k_search_valu_seeded<D, K, 5><<<grid, 256, 0, s>>>(a); break;
+        case 6: k_search_valu_seeded<D, K, 6><<<grid, 256, 0, s>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_search_valu_seeded(const SearchArgs &a, int K, int grid, hipStream_t s) {
+    switch (K) {
+        case 4: return launch_search_valu_seeded_k<D, 4>(a, grid, s);
+        case 5: return launch_search_valu_seeded_k<D, 5>(a, grid, s);
+        case 8: return launch_search_valu_seeded_k<D, 8>(a, grid, s);
+        case 10: return launch_search_valu_seeded_k<D, 10>(a, grid, s);
+        case 11: return launch_search_valu_seeded_k<D, 11>(a, grid, s);
+        case 16: return launch_search_valu_seeded_k<D, 16>(a, grid, s);
+        case 32: return launch_search_valu_seeded_k<D, 32>(a, grid, s);
+        case 50: return launch_search_valu_seeded_k<D, 50>(a, grid, s);
+        case 51: return launch_search_valu_seeded_k<D, 51>(a, grid, s);
+        case 64: return launch_search_valu_seeded_k<D, 64>(a, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace knnx
