@@ -21,9 +21,11 @@
 // beside it for the exact re-score, and its centred row norms -- and every
 // wave whose own leaf keeps it multiplies it against its 32 queries with
 // v_mfma_f32_32x32x16_bf16 (layout, filter margin and FP64 re-score as in
-// k_search_mfma).  After every tile the waves publish their bounds in LDS at
-// the tile barrier; the query node above the four leaves adds the B(Par)
-// term min over all its queries of D_p[k] + 2 lambda(node).
+// k_search_mfma).  The staged tiles are double-buffered: one workgroup
+// barrier per kept leaf publishes the waves' bounds and the last staged
+// tile; after it each wave multiplies that tile, then stages the next kept
+// leaf into the other buffer.  The query node above the four leaves adds the
+// B(Par) term min over all its queries of D_p[k] + 2 lambda(node).
 #pragma once
 
 #include "search_mfma.hpp"
@@ -41,13 +43,16 @@ struct SweepLds {
     static constexpr size_t q_rows = size_t(kWgLeaves) * 32 * DP * 4;
     static constexpr size_t merge = size_t(64) * K * 8;  // one wave's half-lists
     static constexpr size_t region = q_rows > merge ? q_rows : merge;
+    // two buffers of each per-tile array
     static constexpr size_t off_tile_f = 0;
-    static constexpr size_t off_tile_bf = off_tile_f + tile_f;
-    static constexpr size_t off_region = off_tile_bf + tile_bf;
+    static constexpr size_t off_tile_bf = off_tile_f + 2 * tile_f;
+    static constexpr size_t off_region = off_tile_bf + 2 * tile_bf;
     static constexpr size_t off_cen = off_region + region;
     static constexpr size_t off_rn = off_cen + size_t(DP) * 4;
-    static constexpr size_t off_misc = off_rn + 32 * 4;
-    static constexpr size_t bytes = off_misc + 16 * 4;
+    // misc: bounds exchange slots [2 parities][2][kWgLeaves], then the
+    // largest row norm per wave of each tile buffer [2][kWgLeaves]
+    static constexpr size_t off_misc = off_rn + 2 * 32 * 4;
+    static constexpr size_t bytes = off_misc + 32 * 4;
 };
 
 // Two workgroups per CU (two waves per SIMD) where the lists allow it: each
@@ -190,16 +195,21 @@ k_search_mfma_sweep(const SearchArgs a) {
     uint64_t n_pairs = 0;
 
     // publish the waves' bounds, then every wave derives the same
-    // workgroup bound; the barrier also ends every use of the staged tile
+    // workgroup bound.  The barrier also makes the last staged tile visible.
+    // The slots alternate between two parities: a wave may publish the next
+    // exchange's values before a slower wave has read this one's.
+    int xp = 0;
     auto exchange_bounds = [&]() {
+        float *sb = s_misc + xp * 2 * kWgLeaves;
         if (lane == 0) {
-            s_misc[w] = has_leaf ? bound2 : -kInf;
-            s_misc[kWgLeaves + w] = has_leaf ? lo_k : kInf;
+            sb[w] = has_leaf ? bound2 : -kInf;
+            sb[kWgLeaves + w] = has_leaf ? lo_k : kInf;
         }
         lds_barrier();
+        xp ^= 1;
         float lo_all = kInf;
 #pragma unroll
-        for (int g = 0; g < kWgLeaves; ++g) lo_all = fminf(lo_all, s_misc[kWgLeaves + g]);
+        for (int g = 0; g < kWgLeaves; ++g) lo_all = fminf(lo_all, sb[kWgLeaves + g]);
         float bp = kInf;
         if (a.bound == KNN_BOUND_B && lo_all < kInf && lam2_anc < kInf) {
             const float t = sqrtf(lo_all) + lam2_anc;
@@ -207,7 +217,7 @@ k_search_mfma_sweep(const SearchArgs a) {
         }
         bound2 = fminf(bound2, bp);
 #pragma unroll
-        for (int g = 0; g < kWgLeaves; ++g) bnd[g] = uniform_f(fminf(s_misc[g], bp));
+        for (int g = 0; g < kWgLeaves; ++g) bnd[g] = uniform_f(fminf(sb[g], bp));
     };
 
     // d_min^2 between each leaf's box and a reference node's box; a node is
@@ -256,49 +266,53 @@ k_search_mfma_sweep(const SearchArgs a) {
         }
     };
 
-    // one tile from prefetched rows v (this thread's E columns of row trow);
-    // mine: this wave's own leaf keeps the node
-    auto tile = [&](int2 rr, const float (&v)[E], bool mine) {
-        const int base = uniform_i(rr.x);
-        const int cnt = uniform_i(rr.y);
-        // stage: rows past the leaf are zero with an infinite norm (never
-        // candidates)
-        {
-            const bool vrow = trow < cnt;
-            float rn = 0.f;
+    // stage a leaf from prefetched rows v (this thread's E columns of row
+    // trow) into tile buffer b: rows past the leaf are zero with an infinite
+    // norm (never candidates)
+    auto stage = [&](int b, int cnt, const float (&v)[E]) {
+        __bf16 *tb = s_tb + b * 32 * L::kRowBf;
+        float *tf = s_tf + b * 32 * DP;
+        const bool vrow = trow < cnt;
+        float rn = 0.f;
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const float rd = vrow ? v[e] - tc[e] : 0.f;
-                rn = fmaf(rd, rd, rn);
-                s_tb[trow * L::kRowBf + tcol + e] = (__bf16)rd;
-                s_tf[trow * DP + tcol + e] = v[e];
-            }
-            rn = reduce8(rn, OpAdd());
-            if ((tid & 7) == 0) s_rn[trow] = vrow ? rn : kInf;
-            // largest norm of this wave's eight rows
-            const float rm = reduce64(vrow ? rn : 0.f, OpMax());
-            if (lane == 0) s_misc[2 * kWgLeaves + w] = rm;
+        for (int e = 0; e < E; ++e) {
+            const float rd = vrow ? v[e] - tc[e] : 0.f;
+            rn = fmaf(rd, rd, rn);
+            tb[trow * L::kRowBf + tcol + e] = (__bf16)rd;
+            tf[trow * DP + tcol + e] = v[e];
         }
-        lds_barrier();
-        // largest |r'| in the tile (hardware square root, 1 ulp, nudged up:
-        // the margin only needs an upper bound)
-        if (mine) {
+        rn = reduce8(rn, OpAdd());
+        if ((tid & 7) == 0) s_rn[b * 32 + trow] = vrow ? rn : kInf;
+        // largest norm of this wave's eight rows
+        const float rm = reduce64(vrow ? rn : 0.f, OpMax());
+        if (lane == 0) s_misc[4 * kWgLeaves + b * kWgLeaves + w] = rm;
+    };
+    // one staged tile (buffer b, leaf rows base .. base + cnt) against this
+    // wave's queries; own: the d_min^2 of this wave's leaf to the leaf's box,
+    // re-checked against the bound as it stands now
+    auto compute = [&](int b, int base, int cnt, float own) __attribute__((always_inline)) {
+        if (!has_leaf || own > bound2 * kSlack) return;
+        const __bf16 *tb = s_tb + b * 32 * L::kRowBf;
+        const float *tf = s_tf + b * 32 * DP;
+        const float *trn = s_rn + b * 32;
         ++n_tiles;
         n_pairs += uint64_t(cnt) * uint64_t(qcount);
+        // largest |r'| in the tile (hardware square root, 1 ulp, nudged up:
+        // the margin only needs an upper bound)
         float rmax = 0.f;
 #pragma unroll
-        for (int g = 0; g < kWgLeaves; ++g) rmax = fmaxf(rmax, s_misc[2 * kWgLeaves + g]);
+        for (int g = 0; g < kWgLeaves; ++g) rmax = fmaxf(rmax, s_misc[4 * kWgLeaves + b * kWgLeaves + g]);
         const float rlen = __builtin_amdgcn_sqrtf(uniform_f(rmax)) * (1.0f + 0x1p-20f);
         f32x16_t acc;
 #pragma unroll
         for (int g4 = 0; g4 < 4; ++g4) {
-            const float4 v = *reinterpret_cast<const float4 *>(&s_rn[g4 * 8 + h * 4]);
+            const float4 v = *reinterpret_cast<const float4 *>(&trn[g4 * 8 + h * 4]);
             acc[g4 * 4 + 0] = v.x;
             acc[g4 * 4 + 1] = v.y;
             acc[g4 * 4 + 2] = v.z;
             acc[g4 * 4 + 3] = v.w;
         }
-        const __bf16 *arow = s_tb + j * L::kRowBf + h * 8;
+        const __bf16 *arow = tb + j * L::kRowBf + h * 8;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const bf16x8_t ar = *reinterpret_cast<const bf16x8_t *>(arow + s * 16);
@@ -308,6 +322,13 @@ k_search_mfma_sweep(const SearchArgs a) {
         const float lim = fminf(pair_kth, bound2) * kSlack;
         const float marg = kC1 * qlen * rlen + kC2 * (qlen + rlen) * (qlen + rlen);
         const float thr = valid ? lim - qn + marg : -kInf;
+        // most tiles have no candidate at all: one test on the smallest value
+        // of each lane skips the per-row mask, the survivor rounds and the
+        // bound refresh (the lists and so the bounds are unchanged)
+        float amin = acc[0];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) amin = fminf(amin, acc[r]);
+        if (!ballot(amin <= thr)) return;
         // rows past the leaf never count: their +inf would pass a +inf
         // threshold (empty lists)
         uint32_t mask = 0;
@@ -328,14 +349,12 @@ k_search_mfma_sweep(const SearchArgs a) {
             const int r = has ? __builtin_ctz(mask) : 0;
             mask &= mask - 1u;
             const int row = 8 * (r >> 2) + 4 * h + (r & 3);
-            const float x0 = (float)d2_fp64_rows<DP>(my_q, s_tf + row * DP);
+            const float x0 = (float)d2_fp64_rows<DP>(my_q, tf + row * DP);
             const float x = has ? x0 : kInf;
             n_ins += (x < dist[K - 1]) ? 1u : 0u;
             insert(x, base + row);
         }
         refresh_bound();
-        }
-        exchange_bounds();
     };
 
     exchange_bounds();
@@ -394,7 +413,16 @@ k_search_mfma_sweep(const SearchArgs a) {
             v[e + 1] = x.y;
         }
     };
-    // score a fetched leaf and process it when any query leaf keeps it
+    // score a fetched leaf; when any query leaf keeps it: exchange bounds
+    // (the barrier that publishes the tile staged last), stage this leaf
+    // into the other buffer, multiply the tile staged last.  Every wave
+    // takes the same decisions (bnd is the same in all of them), so the
+    // barriers match.  Safety of the two buffers: a wave stages into the
+    // buffer of the tile before last, and every wave finished that tile
+    // before it reached the barrier this wave has just passed.
+    int pend_b = 1, pend_base = 0, pend_cnt = 0;  // the staged, unmultiplied tile
+    float pend_own = kInf;
+    bool pending = false;
     auto visit = [&](int2 rr, float blo, float bhi, const float (&v)[E]) {
         float dm[kWgLeaves];
         score_node(blo, bhi, dm);
@@ -406,7 +434,18 @@ k_search_mfma_sweep(const SearchArgs a) {
             keep |= !(dm[g] > bnd[g] * kSlack);
             own = (w == g) ? dm[g] : own;
         }
-        if (keep) tile(rr, v, has_leaf && !(own > bound2 * kSlack));
+        if (keep) {
+            exchange_bounds();
+            const int b = pend_b ^ 1;
+            const int cnt = uniform_i(rr.y);
+            stage(b, cnt, v);
+            if (pending) compute(pend_b, pend_base, pend_cnt, pend_own);
+            pending = true;
+            pend_b = b;
+            pend_base = uniform_i(rr.x);
+            pend_cnt = cnt;
+            pend_own = own;
+        }
     };
     // two register sets used in turn: a leaf's loads land in the set that
     // the next visit reads, so they stay in flight while the current leaf
@@ -431,6 +470,10 @@ k_search_mfma_sweep(const SearchArgs a) {
             fetch(leaf_or_start(sn), rr_a, blo_a, bhi_a, v_a);
             visit(rr_b, blo_b, bhi_b, v_b);
             sc = sn;
+        }
+        if (pending) {
+            exchange_bounds();
+            compute(pend_b, pend_base, pend_cnt, pend_own);
         }
     }
 
