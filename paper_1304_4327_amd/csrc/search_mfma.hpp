@@ -244,6 +244,14 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
         const float lim = fminf(pair_kth, bound2) * kSlack;
         const float marg = kC1 * qlen * rlen + kC2 * (qlen + rlen) * (qlen + rlen);
         const float thr = lim - qn + marg;
+        // most tiles have no candidate at all: one test on the smallest value
+        // of each lane skips the per-row mask, the survivor rounds and the
+        // bound refresh (the lists and so the bounds are unchanged); rows past
+        // the leaf hold +inf and are masked below when the threshold is +inf
+        float amin = acc[0];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) amin = fminf(amin, acc[r]);
+        if (!ballot(valid && amin <= thr)) return;
         uint32_t mask = 0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
