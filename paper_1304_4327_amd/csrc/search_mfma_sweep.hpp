@@ -122,21 +122,26 @@ k_search_mfma_sweep(const SearchArgs a) {
         }
     }
     if (w == 0 && lane < DP) s_cen[lane] = 0.5f * (ulo + uhi);
-    // each leaf's own box for Score, 64 / DP leaves per round: lane l holds
-    // dimension l % DP of leaf round * (64 / DP) + l / DP (an idle leaf's
-    // box is empty: lo = +inf, hi = -inf, so its d_min is +inf)
-    constexpr int GPR = 64 / DP;             // leaves per round
-    constexpr int ROUNDS = kWgLeaves / GPR;  // 1, 2 or 4
-    float plo[ROUNDS], phi[ROUNDS];
+    // each leaf's own box for Score: 16 lanes per leaf, lane l holds
+    // dimensions (l % 16) * DPL .. + DPL - 1 of leaf l / 16, so one 16-lane
+    // reduction (DPP row operations only) scores a node for all four leaves
+    // (an idle leaf's box is empty: lo = +inf, hi = -inf, so its d_min is
+    // +inf)
+    static_assert(kWgLeaves * 16 == 64, "Score layout: 16 lanes per query leaf");
+    constexpr int DPL = DP / 16;
+    const int sg = lane >> 4, sd = (lane & 15) * DPL;
+    float plo[DPL], phi[DPL];
 #pragma unroll
-    for (int rd = 0; rd < ROUNDS; ++rd) {
-        const int g = rd * GPR + lane / DP;
-        plo[rd] = kInf;
-        phi[rd] = -kInf;
-        if (leaf_on(leaf0 + g)) {
-            const float *qb = a.qbox + int64_t(a.q_first_leaf + leaf0 + g) * 2 * DP;
-            plo[rd] = qb[lane % DP];
-            phi[rd] = qb[DP + lane % DP];
+    for (int e = 0; e < DPL; ++e) {
+        plo[e] = kInf;
+        phi[e] = -kInf;
+    }
+    if (leaf_on(leaf0 + sg)) {
+        const float *qb = a.qbox + int64_t(a.q_first_leaf + leaf0 + sg) * 2 * DP;
+#pragma unroll
+        for (int e = 0; e < DPL; ++e) {
+            plo[e] = qb[sd + e];
+            phi[e] = qb[DP + sd + e];
         }
     }
     // this wave's query rows (FP32) for the exact re-score; zero for idle lanes
@@ -222,22 +227,17 @@ k_search_mfma_sweep(const SearchArgs a) {
 
     // d_min^2 between each leaf's box and a reference node's box; a node is
     // kept when any leaf would keep it (its d_min within that leaf's bound)
-    auto score_node = [&](float lo, float hi, float (&dm)[kWgLeaves]) {
+    auto score_node = [&](const float (&lo)[DPL], const float (&hi)[DPL], float (&dm)[kWgLeaves]) {
+        float sum = 0.f;
 #pragma unroll
-        for (int rd = 0; rd < ROUNDS; ++rd) {
-            const float gap = fmaxf(fmaxf(lo - phi[rd], plo[rd] - hi), 0.0f);
-            float sum;
-            if constexpr (DP <= 16)
-                sum = reduce16(gap * gap, OpAdd());
-            else if constexpr (DP <= 32)
-                sum = reduce32(gap * gap, OpAdd());
-            else
-                sum = reduce64(gap * gap, OpAdd());
-#pragma unroll
-            for (int gi = 0; gi < GPR; ++gi)
-                dm[rd * GPR + gi] = __builtin_bit_cast(
-                    float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sum), gi * DP));
+        for (int e = 0; e < DPL; ++e) {
+            const float gap = fmaxf(fmaxf(lo[e] - phi[e], plo[e] - hi[e]), 0.0f);
+            sum = fmaf(gap, gap, sum);
         }
+        sum = reduce16(sum, OpAdd());
+#pragma unroll
+        for (int g = 0; g < kWgLeaves; ++g)
+            dm[g] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sum), 16 * g));
     };
     auto refresh_bound = [&]() {
         pair_kth = xor32_op(dist[K - 1], OpMin());
@@ -283,9 +283,15 @@ k_search_mfma_sweep(const SearchArgs a) {
         }
         rn = reduce8(rn, OpAdd());
         if ((tid & 7) == 0) s_rn[b * 32 + trow] = vrow ? rn : kInf;
-        // largest norm of this wave's eight rows
-        const float rm = reduce64(vrow ? rn : 0.f, OpMax());
-        if (lane == 0) s_misc[4 * kWgLeaves + b * kWgLeaves + w] = rm;
+        // largest norm of this wave's eight rows: within each 16 lanes by
+        // DPP, then over the four groups on the scalar unit (the norms are
+        // non-negative, so their bit patterns order as unsigned integers)
+        const float r16 = reduce16(vrow ? rn : 0.f, OpMax());
+        uint32_t rmu = 0u;
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            rmu = max(rmu, (uint32_t)__builtin_amdgcn_readlane(__builtin_bit_cast(int, r16), 16 * g));
+        if (lane == 0) s_misc[4 * kWgLeaves + b * kWgLeaves + w] = __builtin_bit_cast(float, rmu);
     };
     // one staged tile (buffer b, leaf rows base .. base + cnt) against this
     // wave's queries; own: the d_min^2 of this wave's leaf to the leaf's box,
@@ -396,12 +402,15 @@ k_search_mfma_sweep(const SearchArgs a) {
     };
     // loads of one leaf: range, this lane's box coordinates, this thread's
     // rows (the leaf-blocked copy has r_leaf_slots <= 32 rows per leaf)
-    auto fetch = [&](int leaf, int2 &rr, float &blo, float &bhi, float (&v)[E]) {
+    auto fetch = [&](int leaf, int2 &rr, float (&blo)[DPL], float (&bhi)[DPL], float (&v)[E]) {
         const int node = a.r_first_leaf + leaf;
         rr = a.rrange[node];
         const float *b = a.rbox + int64_t(node) * 2 * DP;
-        blo = b[lane % DP];
-        bhi = b[DP + lane % DP];
+#pragma unroll
+        for (int e = 0; e < DPL; ++e) {
+            blo[e] = b[sd + e];
+            bhi[e] = b[DP + sd + e];
+        }
         // unconditional loads (a clamped row; rows past the leaf are masked
         // at staging): a load under a branch makes the compiler wait for
         // every load in flight where the paths join
@@ -423,7 +432,7 @@ k_search_mfma_sweep(const SearchArgs a) {
     int pend_b = 1, pend_base = 0, pend_cnt = 0;  // the staged, unmultiplied tile
     float pend_own = kInf;
     bool pending = false;
-    auto visit = [&](int2 rr, float blo, float bhi, const float (&v)[E]) {
+    auto visit = [&](int2 rr, const float (&blo)[DPL], const float (&bhi)[DPL], const float (&v)[E]) {
         float dm[kWgLeaves];
         score_node(blo, bhi, dm);
         ++n_score;
@@ -452,7 +461,9 @@ k_search_mfma_sweep(const SearchArgs a) {
     // is processed (no register copy forces an early wait)
     {
         int2 rr_a = make_int2(0, 0), rr_b = make_int2(0, 0);
-        float blo_a = 0.f, bhi_a = 0.f, blo_b = 0.f, bhi_b = 0.f, v_a[E], v_b[E];
+        float blo_a[DPL], bhi_a[DPL], blo_b[DPL], bhi_b[DPL], v_a[E], v_b[E];
+#pragma unroll
+        for (int e = 0; e < DPL; ++e) blo_a[e] = bhi_a[e] = blo_b[e] = bhi_b[e] = 0.f;
 #pragma unroll
         for (int e = 0; e < E; ++e) v_a[e] = v_b[e] = 0.f;
         // past the last step the fetch repeats the start leaf (in bounds,
