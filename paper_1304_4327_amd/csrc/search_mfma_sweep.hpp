@@ -217,7 +217,8 @@ k_search_mfma_sweep(const SearchArgs a) {
         for (int g = 0; g < kWgLeaves; ++g) lo_all = fminf(lo_all, sb[kWgLeaves + g]);
         float bp = kInf;
         if (a.bound == KNN_BOUND_B && lo_all < kInf && lam2_anc < kInf) {
-            const float t = sqrtf(lo_all) + lam2_anc;
+            // hardware square root (1 ulp): far inside the prune slack
+            const float t = __builtin_amdgcn_sqrtf(lo_all) + lam2_anc;
             bp = t * t;
         }
         bound2 = fminf(bound2, bp);
@@ -247,7 +248,7 @@ k_search_mfma_sweep(const SearchArgs a) {
         lo_k = uniform_f(lo);
         float b = hi;  // B1^2
         if (a.bound == KNN_BOUND_B) {
-            const float b2 = sqrtf(lo) + lam2;
+            const float b2 = __builtin_amdgcn_sqrtf(lo) + lam2;
             b = fminf(b, b2 * b2);
         }
         bound2 = uniform_f(fminf(fminf(b, seed2), bound2));
@@ -283,14 +284,13 @@ k_search_mfma_sweep(const SearchArgs a) {
         }
         rn = reduce8(rn, OpAdd());
         if ((tid & 7) == 0) s_rn[b * 32 + trow] = vrow ? rn : kInf;
-        // largest norm of this wave's eight rows: within each 16 lanes by
-        // DPP, then over the four groups on the scalar unit (the norms are
-        // non-negative, so their bit patterns order as unsigned integers)
-        const float r16 = reduce16(vrow ? rn : 0.f, OpMax());
+        // largest norm of this wave's eight rows (every lane of a row's
+        // eight holds its norm), taken on the scalar unit: the norms are
+        // non-negative, so their bit patterns order as unsigned integers
+        const int rnb = __builtin_bit_cast(int, vrow ? rn : 0.f);
         uint32_t rmu = 0u;
 #pragma unroll
-        for (int g = 0; g < 4; ++g)
-            rmu = max(rmu, (uint32_t)__builtin_amdgcn_readlane(__builtin_bit_cast(int, r16), 16 * g));
+        for (int g = 0; g < 8; ++g) rmu = max(rmu, (uint32_t)__builtin_amdgcn_readlane(rnb, 8 * g));
         if (lane == 0) s_misc[4 * kWgLeaves + b * kWgLeaves + w] = __builtin_bit_cast(float, rmu);
     };
     // one staged tile (buffer b, leaf rows base .. base + cnt) against this
