@@ -175,7 +175,8 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
         const float lo = reduce32(valid ? pair_kth : kInf, OpMin());
         float b = hi;  // B1^2
         if (a.bound == KNN_BOUND_B) {
-            const float b2 = sqrtf(lo) + lam2;
+            // hardware square root (1 ulp): far inside the prune slack
+            const float b2 = __builtin_amdgcn_sqrtf(lo) + lam2;
             b = fminf(b, b2 * b2);
         }
         bound2 = uniform_f(fminf(b, seed2));
@@ -222,7 +223,13 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
             }
         }
         rn = xor32_op(rn, OpAdd());
-        const float rmax = reduce32(vr ? rn : 0.f, OpMax());
+        // largest norm of the tile: over each 16 rows by DPP, then the two
+        // halves on the scalar unit (non-negative floats order as unsigned
+        // integers)
+        const float r16 = reduce16(vr ? rn : 0.f, OpMax());
+        const float rmax = __builtin_bit_cast(
+            float, max((uint32_t)__builtin_amdgcn_readlane(__builtin_bit_cast(int, r16), 0),
+                       (uint32_t)__builtin_amdgcn_readlane(__builtin_bit_cast(int, r16), 16)));
         // hardware square root (1 ulp), nudged up: the margin only needs an
         // upper bound
         const float rlen = __builtin_amdgcn_sqrtf(uniform_f(rmax)) * (1.0f + 0x1p-20f);
