@@ -288,10 +288,6 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     // point, CH points per batch.  A candidate must beat min(D_p[k], B):
     // B bounds the point's final k-th distance, so anything farther cannot
     // enter its final list (equal distances aside).
-    // BaseCase over one reference leaf: every lane against each reference
-    // point, CH points per batch.  A candidate must beat min(D_p[k], B):
-    // B bounds the point's final k-th distance, so anything farther cannot
-    // enter its final list (equal distances aside).
     constexpr int CH = DP >= 32 ? 1 : 32 / DP;
     auto tile = [&](int node) {
         ++n_tiles;

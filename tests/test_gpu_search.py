@@ -164,6 +164,25 @@ def test_bf16_dims_and_self(d, k):
     _check(ref, q, k, gi, gd)
 
 
+@pytest.mark.parametrize("n_ref,n_q,k,leaf", [(20, 5, 7, 32), (700, 5, 7, 32), (700, 70, 3, 16),
+                                             (3000, 200, 50, 32)])
+def test_bf16_sweep_small_and_idle_waves(n_ref, n_q, k, leaf):
+    """d = 64 leaf sweep at shapes that reach its edges: one reference leaf
+    (only the flush after the sweep multiplies a tile), workgroups whose
+    four query leaves are not all present (idle waves still stage and meet
+    at every barrier), and lists of 50 with many kept leaves."""
+    rng = np.random.default_rng(n_ref + 7 * n_q + k)
+    basis = rng.standard_normal((6, 64))
+    ref = (rng.random((n_ref, 6)) @ basis + 0.05 * rng.standard_normal((n_ref, 64))).astype(np.float32)
+    q = (rng.random((n_q, 6)) @ basis + 0.05 * rng.standard_normal((n_q, 64))).astype(np.float32)
+    kk = min(k, n_ref - 1)
+    gi, gd, _ = _search(ref, q, kk, leaf, precision="bf16")
+    _check(ref, q, kk, gi, gd)
+    for bound in ("B1", "none"):
+        gi2, gd2, _ = _search(ref, q, kk, leaf, bound=bound, precision="bf16")
+        assert np.array_equal(gi, gi2) and np.array_equal(gd, gd2)
+
+
 def test_bf16_same_answer_as_fp32():
     ref, q, k, leaf = datagen.make("manifold4m_d16_k10", scale=0.004)
     a = _search(ref, q, k, leaf, precision="fp32")
