@@ -192,7 +192,8 @@ k_search_mfma_sweep(const SearchArgs a) {
     }
     float bound2 = (a.bound == KNN_BOUND_NONE) ? kInf : seed2;  // this wave's B^2
     float lo_k = kInf;      // min over the wave's queries of D_p[k]^2
-    float bnd[kWgLeaves];   // every leaf's pruning bound (squared), the same in all waves
+    float bnd[kWgLeaves];   // every leaf's pruning bound (squared, times the prune
+                            // slack), the same in all waves
 #pragma unroll
     for (int g = 0; g < kWgLeaves; ++g) bnd[g] = kInf;
     float pair_kth = kInf;  // min of the two half-list k-ths of this query
@@ -223,7 +224,7 @@ k_search_mfma_sweep(const SearchArgs a) {
         }
         bound2 = fminf(bound2, bp);
 #pragma unroll
-        for (int g = 0; g < kWgLeaves; ++g) bnd[g] = uniform_f(fminf(sb[g], bp));
+        for (int g = 0; g < kWgLeaves; ++g) bnd[g] = uniform_f(fminf(sb[g], bp) * kSlack);
     };
 
     // d_min^2 between each leaf's box and a reference node's box; a node is
@@ -436,11 +437,13 @@ k_search_mfma_sweep(const SearchArgs a) {
         float dm[kWgLeaves];
         score_node(blo, bhi, dm);
         ++n_score;
-        bool keep = false;
+        // wave-uniform tests: ballots of uniform compares go straight into
+        // a scalar mask
+        uint64_t keep = 0;
         float own = dm[0];
 #pragma unroll
         for (int g = 0; g < kWgLeaves; ++g) {
-            keep |= !(dm[g] > bnd[g] * kSlack);
+            keep |= ballot(!(dm[g] > bnd[g]));
             own = (w == g) ? dm[g] : own;
         }
         if (keep) {
