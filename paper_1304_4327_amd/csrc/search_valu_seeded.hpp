@@ -311,7 +311,9 @@ __global__ __launch_bounds__(256) void k_search_valu_seeded(const SearchArgs a) 
     int s_ins = 0;
     bool fb_q = false, fb_leaf = false;  // this lane's query / leaf missed its seed
     bool second = false;                 // a second pass ran in this wave
-    auto walk = [&]() {
+    // (a loop of at most two passes around the walk: as a closure called
+    // twice, the walk made this kernel much slower)
+    for (int pass = 0;; ++pass) {
     {
         float dm0, dm1;
         int node = 0, depth = 0;
@@ -367,38 +369,33 @@ __global__ __launch_bounds__(256) void k_search_valu_seeded(const SearchArgs a) 
             }
         }
     }
-    };
-    walk();
-    {
+        if (pass > 0) break;
         // seed check on the list (FP32 squared distances: their error is far
         // inside the check's factor)
         fb_q = valid && !(dist[K - 1] <= seed2 * (1.0f - 0x1p-18f));
-        if (ballot(fb_q)) {
-            float f = fb_q ? 1.0f : 0.0f;
-            for (int l = 0; l < lpl_log2; ++l) f = xor_level(f, l, OpMax());
-            fb_leaf = valid && f > 0.0f;
-            // proven bound for the leaf: min over its full lists of D_p[k]
-            // plus 2 lambda (the B2 argument holds whatever seed built the
-            // lists)
-            float kb = (valid && dist[K - 1] < kInf) ? __builtin_amdgcn_sqrtf(dist[K - 1]) : kInf;
-            for (int l = 0; l < lpl_log2; ++l) kb = xor_level(kb, l, OpMin());
-            const float pb = (kb + lam2) * (1.0f + 0x1p-18f);
-            second = true;
-            s_score = n_score;
-            s_tiles = n_tiles;
-            s_pairs = n_pairs;
-            s_ins = n_ins;
+        if (!ballot(fb_q)) break;
+        float f = fb_q ? 1.0f : 0.0f;
+        for (int l = 0; l < lpl_log2; ++l) f = xor_level(f, l, OpMax());
+        fb_leaf = valid && f > 0.0f;
+        // proven bound for the leaf: min over its full lists of D_p[k] plus
+        // 2 lambda (the B2 argument holds whatever seed built the lists)
+        float kb = (valid && dist[K - 1] < kInf) ? __builtin_amdgcn_sqrtf(dist[K - 1]) : kInf;
+        for (int l = 0; l < lpl_log2; ++l) kb = xor_level(kb, l, OpMin());
+        const float pb = (kb + lam2) * (1.0f + 0x1p-18f);
+        second = true;
+        s_score = n_score;
+        s_tiles = n_tiles;
+        s_pairs = n_pairs;
+        s_ins = n_ins;
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                dist[j] = fb_leaf ? ((j < K - kk) ? -kInf : kInf) : dist[j];
-                idx[j] = fb_leaf ? -1 : idx[j];
-            }
-            valid = fb_leaf;
-            n_valid = __popcll(ballot(valid));
-            seed2 = kInf;
-            bound2 = (a.bound == KNN_BOUND_NONE || !fb_leaf) ? kInf : pb * pb;
-            walk();
+        for (int j = 0; j < K; ++j) {
+            dist[j] = fb_leaf ? ((j < K - kk) ? -kInf : kInf) : dist[j];
+            idx[j] = fb_leaf ? -1 : idx[j];
         }
+        valid = fb_leaf;
+        n_valid = __popcll(ballot(valid));
+        seed2 = kInf;
+        bound2 = (a.bound == KNN_BOUND_NONE || !fb_leaf) ? kInf : pb * pb;
     }
     valid = valid0;
 
