@@ -63,3 +63,20 @@ def test_excuses_exact_ties():
     f, _ = parity.check(x, x, 1, np.array([[0], [0], [0], [0]]), np.sqrt(d2), idx, d2,
                         exclude_self=True)
     assert f["self_match"] >= 1
+
+
+def test_rejects_beyond_kth_inside_a_tie():
+    """A tie at the k-th place hides a planted far entry from the
+    missing-neighbour test (neither tied point is required), so only the
+    upper-bound test can see it: query 0 has neighbours 1 and 2 at distance
+    1 (a tie at k = 1) and 3 at distance 2."""
+    x = np.array([[0, 0], [1, 0], [0, 1], [2, 0], [5, 5]], np.float32)
+    idx, d2 = ok.knn(x, x, 1, exclude_self=True)
+    gi = idx.copy()
+    gd = np.sqrt(d2).astype(np.float32)
+    gi[0, 0] = 3
+    gd[0, 0] = 2.0
+    f, _ = parity.check(x, x, 1, gi, gd, idx, d2, exclude_self=True)
+    assert f["missing_neighbour"] == 0
+    assert f["beyond_kth"] == 1
+    assert sum(f.values()) == 1

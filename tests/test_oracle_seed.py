@@ -38,3 +38,32 @@ def test_self_descent_reaches_own_leaf():
             r = b if sf._box_d2(t["lo"][b], t["hi"][b], c) < sf._box_d2(t["lo"][a], t["hi"][a], c) else a
         own += r == node
     assert own >= 0.95 * (1 << t["depth"])
+
+
+def _read_fixture(path):
+    ref, qry, feats, leaf = [], [], [], None
+    for line in open(path):
+        t = line.split("#", 1)[0].split()
+        if not t:
+            continue
+        if t[0] == "ref":
+            ref.append([float(v) for v in t[1:]])
+        elif t[0] == "query":
+            qry.append([float(v) for v in t[1:]])
+        elif t[0] == "feature":
+            feats.append([float(v) for v in t[1:]])
+        elif t[0] == "leaf_size":
+            leaf = int(t[1])
+    return (np.array(ref, np.float32), np.array(qry, np.float32), np.array(feats), leaf)
+
+
+def test_features_of_hand_built_tree(golden_dir):
+    """Hand-derived features of a tiny tree pair: leaf centres, lambda,
+    counts and the density of the reference leaf that the nearer-child
+    descent reaches (distinct densities on both sides of each descent
+    choice, so a wrong centre or a wrong child choice changes the value)."""
+    import os
+    ref, qry, want, leaf = _read_fixture(os.path.join(golden_dir, "seed_features_tiny.txt"))
+    got = sf.features(kd.build(ref, leaf), kd.build(qry, leaf))
+    assert got.shape == want.shape
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
