@@ -8,8 +8,16 @@ the learned seed the trees are built first, the seed network runs on them,
 then the search.  W untimed warm-up steps, then K timed steps between device
 synchronisations.  Prints ONE JSON line.
 
-Default workload: 1,000,000 reference x 1,000,000 query points, d = 3,
+Headline workload: 1,000,000 reference x 1,000,000 query points, d = 3,
 32-component Gaussian mixture, k = 10, leaf size 32, FP32 path.
+
+The second half of the metric -- learned seed + BF16 tiles against the plain
+FP32 traversal -- is measured on the workload where the combined variant is
+defined (1,000,000 reference x 262,144 query points on a 10-dim manifold in
+d = 64, k = 50) and reported in the "compare" object, with the plain BF16
+variant and the classic B1 bound beside it.  Every timed variant's answer is
+checked against the FP64 oracle on the seeded sample that the CPU baseline
+times.
 
 The dominant kernel is the traversal kernel; its average duration comes
 from HIP events the library records around that launch on the same stream
@@ -44,6 +52,8 @@ TRAFFIC_BYTES_PER_LAUNCH = {
     ("gmm1m_d3_k10", "fp32"): int((343733.1875 * 2.000 + 158809.5 * 1.000) * 1024),
 }
 
+COMBINED_WORKLOAD = "manifold1m_d64_k50"
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -65,6 +75,9 @@ def parse():
     ap.add_argument("--compare", action="store_true",
                     help="also time the plain FP32 path on the same workload and report "
                          "the speedup of the chosen variant over it")
+    ap.add_argument("--no-combined", action="store_true",
+                    help="skip the learned+BF16 vs plain FP32 comparison on the d = 64 workload")
+    ap.add_argument("--combined-train-seeds", type=int, default=4)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (reference "
                          "kernel for scaling the HBM byte counters) and exit")
@@ -84,12 +97,15 @@ def copy_calibration(mib):
                                            "launches": 3}}))
 
 
-def cpu_baseline(ref, q, k, self_mode, target_s):
+def cpu_baseline(ref, q, k, self_mode, target_s, answers=None):
     """The oracle (FP64 brute force, OpenMP, all host cores) timed on a
-    seeded sample of the same queries; scaled to queries/s."""
+    seeded sample of the same queries, scaled to queries/s.  The same
+    sample then checks each GPU answer in ``answers`` ({name: (idx, dist)},
+    host arrays) with the acceptance predicate."""
     import numpy as np
 
     from oracle import knn as ok
+    from oracle import parity
     qq = ref if self_mode else q
     rng = np.random.default_rng(1234)
     n = 64
@@ -97,17 +113,101 @@ def cpu_baseline(ref, q, k, self_mode, target_s):
     while True:
         rows = np.sort(rng.choice(len(qq), size=min(n, len(qq)), replace=False))
         t0 = time.perf_counter()
-        ok.knn_rows(qq, rows, ref, k, exclude_self=self_mode)
+        oi, od = ok.knn_rows(qq, rows, ref, k, exclude_self=self_mode)
         elapsed = time.perf_counter() - t0
         if elapsed >= 0.8 * target_s or n >= len(qq):
             break
         # next sample sized for the target (growth capped, so a slow first
         # estimate cannot overshoot far)
         n = int(min(len(qq), n * min(16.0, max(1.5, target_s / max(elapsed, 1e-3) * 1.05))))
-    return {"value": len(rows) / elapsed, "unit": "queries/s", "cores": ok.threads(),
-            "kind": "oracle",
-            "sample": f"{len(rows)} seeded queries x all {len(ref)} references "
-                      f"(FP64 brute force), {elapsed:.2f} s"}
+    out = {"value": len(rows) / elapsed, "unit": "queries/s", "cores": ok.threads(),
+           "kind": "oracle",
+           "sample": f"{len(rows)} seeded queries x all {len(ref)} references "
+                     f"(FP64 brute force), {elapsed:.2f} s"}
+    if answers:
+        out["parity"] = {}
+        for name, (gi, gd) in answers.items():
+            fails, info = parity.check(qq, ref, k, gi, gd, oi, od, rows=rows,
+                                       exclude_self=self_mode)
+            out["parity"][name] = {"rows": info["rows"], "ok": not any(fails.values()),
+                                   "identical_sets": info["identical_sets"],
+                                   "failures": {a: b for a, b in fails.items() if b}}
+    return out
+
+
+def _timed(run, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    sts = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sts.append(run())
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3, sts
+
+
+def combined(args):
+    """Learned seed + BF16 tiles against the plain FP32 traversal on the d = 64
+    workload (plus plain BF16, and the B1 bound), every variant checked."""
+    import numpy as np
+    import torch
+
+    from paper_1304_4327_amd import datagen, knn
+    from paper_1304_4327_amd import seed as S
+    name = COMBINED_WORKLOAD
+    ref, q, k, leaf = datagen.make(name)
+    R, Q = torch.from_numpy(ref).cuda(), torch.from_numpy(q).cuda()
+    nq = len(q)
+    base = datagen.DEFAULT_SEEDS[name]
+    seeds = [base + 100 + i for i in range(args.combined_train_seeds)]
+    t0 = time.perf_counter()
+    model = S.train_for_workload(name, seeds, epochs=args.train_epochs, precision="bf16",
+                                 target_fallback=args.target_fallback)
+    train_s = time.perf_counter() - t0
+
+    def plain(precision, bound="B"):
+        return lambda: knn.knn_all_knn(R, Q, k, leaf, bound=bound, precision=precision,
+                                       stats=True)
+
+    def learned():
+        rt, qt = knn.knn_build_tree_pair(R, Q, leaf)
+        rad = S.radii(model, knn.knn_seed_features(rt, qt))
+        out = knn.knn_search(rt, qt, k, precision="bf16", seed_radius=rad, stats=True)
+        qt.close()
+        rt.close()
+        return out
+
+    res, answers = {}, {}
+    for key, run, steps, warm in (("plain_fp32", plain("fp32"), 2, 1),
+                                  ("learned_bf16", learned, 4, 1),
+                                  ("plain_bf16", plain("bf16"), 4, 1),
+                                  ("plain_bf16_B1", plain("bf16", "B1"), 2, 1)):
+        ms, outs = _timed(run, steps, warm)
+        sts = [o[2] for o in outs]
+        res[key] = {"ms_per_step": ms, "queries_per_s": nq / ms * 1e3,
+                    "pairs_per_query": float(np.mean([s["pairs"] for s in sts])) / nq,
+                    "score_calls_per_query": float(np.mean([s["score_calls"] for s in sts])) / nq,
+                    "ms_search": float(np.mean([s["ms_search"] for s in sts]))}
+        if key == "learned_bf16":
+            res[key]["fallback_leaves"] = float(np.mean([s["fallback_leaves"] for s in sts]))
+            res[key]["query_leaves"] = sts[0]["n_query_leaves"]
+        answers[key] = (outs[-1][0].cpu().numpy(), outs[-1][1].cpu().numpy())
+    line = {"workload": name, "n_ref": len(ref), "n_query": nq, "d": ref.shape[1], "k": k,
+            "baseline": "plain FP32 dual-tree traversal, bound B",
+            "speedup_learned_bf16_vs_plain_fp32":
+                res["plain_fp32"]["ms_per_step"] / res["learned_bf16"]["ms_per_step"],
+            "speedup_plain_bf16_vs_plain_fp32":
+                res["plain_fp32"]["ms_per_step"] / res["plain_bf16"]["ms_per_step"],
+            "bound_B_vs_B1_pairs_per_query": [res["plain_bf16"]["pairs_per_query"],
+                                              res["plain_bf16_B1"]["pairs_per_query"]],
+            "variants": res,
+            "seed_training": {"train_seeds": seeds, "eval_seed": base, "train_s": train_s,
+                              "log_margin": model.log_margin}}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(ref, q, k, False, 5.0, answers)
+    return line
 
 
 def main():
@@ -189,6 +289,7 @@ def main():
     total, stats = timed(args.precision, args.steps, args.warmup, args.learned)
     ms_step = total / args.steps * 1e3
     value = nq * args.steps / total
+    answer = (idx.cpu().numpy(), dist.cpu().numpy())
     compare = None
     if args.compare:
         base_total, base_stats = timed("fp32", max(1, min(args.steps, 2)), 1)
@@ -213,7 +314,7 @@ def main():
     achieved = pairs * flop_per_pair / (kern_ms * 1e-3) / 1e12
     traffic = None if args.learned else TRAFFIC_BYTES_PER_LAUNCH.get((args.workload, args.precision))
     line = {
-        "metric": "exact kNN queries/s, 1M\u00d71M d=3 k=10; learned+BF16 vs plain FP32 speedup",
+        "metric": "exact kNN queries/s, 1M×1M d=3 k=10; learned+BF16 vs plain FP32 speedup",
         "value": value,
         "unit": "queries/s",
         "n_gpus": 1,
@@ -251,8 +352,14 @@ def main():
                                fallback_pairs_per_query=float(np.mean([s["fallback_pairs"] for s in stats])) / nq,
                                ms_seeded_pass=float(np.mean([s["ms_main_kernel"] for s in stats])),
                                ms_search_total=float(np.mean([s["ms_search"] for s in stats])))
+    print(f"headline done: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(ref, q, k, self_mode, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(ref, q, k, self_mode, args.cpu_seconds,
+                                            {"headline": answer})
+    del R, Q, idx, dist
+    if not args.no_combined and args.workload != COMBINED_WORKLOAD:
+        torch.cuda.empty_cache()
+        line["compare_learned_bf16"] = combined(args)
     print(json.dumps(line), flush=True)
 
 

@@ -271,6 +271,53 @@ knn_status knn_seed_features(const knn_tree *ref, const knn_tree *query, float *
 knn_status knn_seed_radius(const knn_mlp *mlp, const float *feats, int64_t n, float log_margin,
                            float *radius, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Test exports.  They run pieces of the search kernels on inputs the caller
+ * chooses, so that tests can check them against the paper's definitions.
+ * ------------------------------------------------------------------------ */
+
+/* The BF16 distance tile of the matrix-core BaseCase (Algorithm 2 distance
+ * evaluation; BF16 tiles themselves are this library's addition), computed by
+ * the same device code as the search kernels, for n_tiles independent tiles.
+ * Tile t: query rows q[t*32 .. t*32+31] and reference rows r[t*32 .. +31]
+ * (device, row-major, d FP32 values per row), centre[t*d .. +d-1] (device).
+ * Outputs (device, caller-owned):
+ *   acc_out    n_tiles x 32 x 32, [t][i][j] = ||r_i - c||^2 - 2 <r_i - c, q_j - c>
+ *              as the matrix unit computed it (BF16 operands, FP32 sums);
+ *   qnorm_out  n_tiles x 32, ||q_j - c||^2 in FP32;
+ *   margin_out n_tiles x 32, the margin M_j the kernels subtract: the tile's
+ *              estimate acc + qnorm of ||q_j - r_i||^2 is claimed to lie within
+ *              M_j of the exact value for every row i of the tile.
+ * Domain: 9 <= d <= 64, 1 <= n_tiles <= 2^24.  Errors: KNN_E_INVALID_ARG,
+ * KNN_E_DEVICE. */
+knn_status knn_debug_bf16_tiles(const float *q, const float *r, const float *centre,
+                                int64_t n_tiles, int32_t d, float *acc_out, float *qnorm_out,
+                                float *margin_out, void *stream);
+
+/* knn_search with its traversal instrumented, for checking the correctness
+ * argument of the k-NN Score (Section "k-Nearest Neighbor Search", the
+ * argument after Algorithm 3: the bound B(N_q) never falls below the largest
+ * true k-th distance of the node's points, so a pruned node pair holds no
+ * true neighbour) and the independence of the answer from the visit order
+ * (Algorithm 4 takes the closer child first; any order gives the same
+ * answer).  Runs the FP32 kernel built with a Score log, for d = 3, no seed,
+ * k-lists of at most 16 entries (k <= 16, or k <= 15 with exclude_self).
+ * far_first: 0 enters the nearer reference child first (as knn_search), 1
+ * the farther one.  log_out (device, capacity x 12 uint32): one record per
+ * Score call, in the order the kernel wrote them:
+ *   [0] reference node (heap order)   [1] 1 if kept, 0 if pruned
+ *   [2] first query leaf of the wavefront  [3] number of query leaves g of
+ *       the wavefront (consecutive leaves)
+ *   [4 .. 4+g-1] FP32 bits of B(N_q)^2 of each of those leaves at that call
+ *       (+inf before the first tile; the per-point bound is min(D_p[k]^2, it))
+ * *n_records (host) receives the number of Score calls; records beyond
+ * capacity are dropped.  Outputs idx_out, dist_out as knn_search.  Errors as
+ * knn_search, KNN_E_UNSUPPORTED outside the covered domain. */
+knn_status knn_debug_search_log(const knn_tree *ref, const knn_tree *query, int32_t k,
+                                const knn_opts *opts, int32_t far_first, uint32_t *log_out,
+                                int64_t capacity, int64_t *n_records, int64_t *idx_out,
+                                float *dist_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import subprocess
 import sys
 
@@ -32,8 +33,27 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src):
+def _deps(path, seen=None):
+    """The file and every local header it includes, recursively."""
+    seen = set() if seen is None else seen
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    for inc in re.findall(r'^\s*#\s*include\s+"([^"]+)"', open(path).read(), flags=re.M):
+        for d in (os.path.dirname(path), CSRC, INCLUDE):
+            cand = os.path.join(d, inc)
+            if os.path.exists(cand):
+                _deps(cand, seen)
+                break
+    return seen
+
+
+def _compile(src, force=True):
     obj = os.path.join(OBJ, os.path.basename(src)[:-4] + ".o")
+    if not force and os.path.exists(obj):
+        newest = max(os.path.getmtime(f) for f in _deps(src))
+        if os.path.getmtime(obj) >= newest:
+            return obj
     cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -41,12 +61,14 @@ def _compile(src):
     return obj
 
 
-def build(jobs: int | None = None) -> str:
+def build(jobs: int | None = None, force: bool = True) -> str:
+    """Compile every source and link.  force=False recompiles only sources
+    whose object is older than the source or a header it includes."""
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, force), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -57,4 +79,5 @@ def build(jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    print(build(int(sys.argv[1]) if len(sys.argv) > 1 else None))
+    args = [a for a in sys.argv[1:] if a != "--incremental"]
+    print(build(int(args[0]) if args else None, force="--incremental" not in sys.argv))

@@ -126,7 +126,7 @@ knn_status validate_tree(const knn_tree *t, const char *who) {
 }  // namespace
 
 knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_opts *opts_in,
-                  int64_t *idx_out, float *dist_out, hipStream_t s) {
+                  int64_t *idx_out, float *dist_out, hipStream_t s, DebugReq *dbg) {
     KNN_TRY(validate_tree(ref, "knn_search"));
     knn_opts opts;
     knn_opts_default(&opts);
@@ -164,6 +164,10 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     }
     const int NG = 64 >> lpl_log2;
     const int nq_leaves = int(qt->n_leaves);
+    if (dbg && (ref->d != 3 || bf16 || opts.seed_radius || K > 16))
+        return fail(KNN_E_UNSUPPORTED,
+                    "knn_debug_search_log: the debug kernel covers d = 3, FP32, no seed, "
+                    "lists of at most 16");
 
     Scratch sc{s, {}};
     unsigned long long *dstats = nullptr;
@@ -210,6 +214,15 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     const char *wlog_path = std::getenv("KNN_WAVE_LOG");
     uint32_t *wlog = nullptr;
 
+    if (dbg) {
+        unsigned int *cnt = nullptr;
+        KNN_HIP(sc.get(&cnt, 1));
+        KNN_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned int), s));
+        a.dbg_log = dbg->log;
+        a.dbg_count = cnt;
+        a.dbg_cap = int(std::min<int64_t>(dbg->cap, INT32_MAX));
+        a.far_first = dbg->far_first;
+    }
     const int waves = (nq_leaves + NG - 1) / NG;
     const int grid = (waves + 3) / 4;
     if (wlog_path) {
@@ -237,7 +250,9 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
         }
     } eg{ev};
     KNN_HIP(hipEventRecord(ev[0], s));
-    KNN_HIP(bf16 ? launch_mfma(a, ref->dp, K, grid, s) : launch_valu(a, ref->d, K, grid, s));
+    KNN_HIP(dbg    ? launch_search_valu_debug_d3(a, K, grid, s)
+            : bf16 ? launch_mfma(a, ref->dp, K, grid, s)
+                   : launch_valu(a, ref->d, K, grid, s));
     KNN_HIP(hipEventRecord(ev[1], s));
     if (opts.seed_radius) {
         k_count_flags<<<(nq_leaves + 255) / 256, 256, 0, s>>>(fb_flag, nq_leaves, fb_count);
@@ -261,7 +276,11 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     if (dstats)
         KNN_HIP(hipMemcpyAsync(hst, dstats, sizeof(hst), hipMemcpyDeviceToHost, s));
     if (fb_count) KNN_HIP(hipMemcpyAsync(&hfb, fb_count, sizeof(int), hipMemcpyDeviceToHost, s));
+    unsigned int hdbg = 0;
+    if (dbg)
+        KNN_HIP(hipMemcpyAsync(&hdbg, a.dbg_count, sizeof(hdbg), hipMemcpyDeviceToHost, s));
     KNN_HIP(hipStreamSynchronize(s));
+    if (dbg) dbg->n_records = int64_t(hdbg);
     if (wlog) {
         std::vector<uint32_t> h(size_t(grid) * 32);
         KNN_HIP(hipMemcpy(h.data(), wlog, h.size() * 4, hipMemcpyDeviceToHost));
@@ -396,6 +415,21 @@ knn_status knn_search(const knn_tree *ref, const knn_tree *query, int32_t k,
                       const knn_opts *opts, int64_t *idx_out, float *dist_out, void *stream) {
     set_error("");
     return search(ref, query, k, opts, idx_out, dist_out, (hipStream_t)stream);
+}
+
+knn_status knn_debug_search_log(const knn_tree *ref, const knn_tree *query, int32_t k,
+                                const knn_opts *opts, int32_t far_first, uint32_t *log_out,
+                                int64_t capacity, int64_t *n_records, int64_t *idx_out,
+                                float *dist_out, void *stream) {
+    set_error("");
+    if (!n_records || (capacity > 0 && !log_out) || capacity < 0)
+        return fail(KNN_E_INVALID_ARG, "knn_debug_search_log: bad log arguments");
+    if (far_first != 0 && far_first != 1)
+        return fail(KNN_E_INVALID_ARG, "knn_debug_search_log: far_first must be 0 or 1");
+    DebugReq dbg{far_first, log_out, capacity, 0};
+    knn_status st = search(ref, query, k, opts, idx_out, dist_out, (hipStream_t)stream, &dbg);
+    *n_records = dbg.n_records;
+    return st;
 }
 
 knn_status knn_search_points(const knn_tree *ref, const float *queries, int64_t n_q, int32_t k,

@@ -159,9 +159,16 @@ void free_tree(knn_tree *t);
 knn_status all_knn(const float *ref_points, int64_t n_ref, const float *query_points,
                    int64_t n_query, int d, int leaf, int k, const knn_opts *opts,
                    int64_t *idx_out, float *dist_out, hipStream_t s);
+// debug requests of knn_debug_search_log: visit order and the Score log
+struct DebugReq {
+    int far_first;
+    uint32_t *log;       // device, cap records
+    int64_t cap;
+    int64_t n_records;   // out: records the kernel produced (may exceed cap)
+};
 // the search of an existing pair of trees (api.hip)
 knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_opts *opts,
-                  int64_t *idx_out, float *dist_out, hipStream_t s);
+                  int64_t *idx_out, float *dist_out, hipStream_t s, DebugReq *dbg = nullptr);
 
 // Device memory for trees and scratch comes from the library's caching
 // allocator (memory.hip): stream-ordered reuse of released blocks.

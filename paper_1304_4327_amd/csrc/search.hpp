@@ -53,7 +53,20 @@ struct SearchArgs {
                                 // seed adds its second pass's counts to the next
                                 // ST_COUNT
     uint32_t *wave_log;         // debug: 8 words per wave (ticks, scores, tiles, inserts, passes, leaf)
+    // Score log of the debug kernel (launch_search_valu_debug_d3): one
+    // record of kDbgWords words per Score call, or NULL; and the visit order
+    // (0: nearer child first, 1: farther child first)
+    uint32_t *dbg_log;
+    unsigned int *dbg_count;  // records written (may exceed dbg_cap: then truncated)
+    int dbg_cap;              // capacity in records
+    int far_first;
 };
+
+// Score-log record: node, kept (1/0), first query leaf of the wave, number
+// of leaves of the wave, then the squared bound B(N_q)^2 of each leaf (as
+// FP32 bits) at the time of the call
+constexpr int kDbgWords = 12;
+constexpr int kDbgMaxLeaves = kDbgWords - 4;
 
 // per-dimension launchers (search_d*.hip): D computed dimensions (d for
 // d <= 4, else d rounded up to 8, 16, 32 or 64 with zero padding); K is
@@ -75,6 +88,10 @@ hipError_t launch_search_valu_seeded_d8(const SearchArgs &a, int K, int grid, hi
 hipError_t launch_search_valu_seeded_d16(const SearchArgs &a, int K, int grid, hipStream_t s);
 hipError_t launch_search_valu_seeded_d32(const SearchArgs &a, int K, int grid, hipStream_t s);
 hipError_t launch_search_valu_seeded_d64(const SearchArgs &a, int K, int grid, hipStream_t s);
+
+// the d = 3 FP32 kernel with the Score log and the visit-order switch
+// (search_debug_d3.hip); lists up to 16
+hipError_t launch_search_valu_debug_d3(const SearchArgs &a, int K, int grid, hipStream_t s);
 
 // BF16 MFMA kernels (search_mfma_d*.hip), stride 16, 32 or 64
 hipError_t launch_search_mfma_dp16(const SearchArgs &a, int K, int grid, hipStream_t s);

@@ -19,26 +19,21 @@
 //   k-th distance is taken as the smaller of its two half-list k-ths (the
 //   k-th of the union cannot exceed either).
 //
-// Filter (exactness).  With u_b = 2^-8 (BF16 round to nearest) and
-// u = 2^-24, |D + ||q'||^2 - ||q - r||^2| <= 2 (2 u_b + u_b^2) |q'| |r'| +
-// (d + 8) u (|q'| + |r'|)^2, the products of BF16 values being exact in FP32
-// and the FP32 sums, the FP32 centring and the norms contributing the second
-// term.  The margin M_j uses that bound with |r'| <= R (largest in the tile),
-// times 1.25.  A pair is kept when D - M_j + ||q_j'||^2 <= T_j with T_j =
-// min(D_j[k], B)^2 (1 + 2^-16); a kept pair is re-scored exactly in FP64 from
-// the FP32 inputs before it may enter a list.  So the BF16 value only decides
-// which pairs are re-scored; lists hold FP64-exact distances.
+// Filter (exactness).  The margin M_j of bf16_tile.hpp bounds the BF16
+// error of each pair of the tile.  A pair is kept when D - M_j + ||q_j'||^2
+// <= T_j with T_j = min(D_j[k], B)^2 (1 + 2^-16); a kept pair is re-scored
+// exactly in FP64 from the FP32 inputs before it may enter a list.  So the
+// BF16 value only decides which pairs are re-scored; lists hold FP64-exact
+// distances.
 //
 // Score uses the query leaf's box (wave-uniform, lanes over dimensions) and
 // B(N_q) = min(B1, min D_p[k] + 2 lambda, seed).
 #pragma once
 
+#include "bf16_tile.hpp"
 #include "search_valu.hpp"
 
 namespace knnx {
-
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 // dynamic LDS per wave: the leaf centre (DP floats), the tile's row norms
 // (32 floats) and, at write-out, both half-lists (64 lanes x K keys + indices)
@@ -72,9 +67,6 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
     constexpr int S = DP / 16;  // k-steps of 16 dimensions
     constexpr float kInf = __builtin_inff();
     constexpr float kSlack = 1.0f + 0x1p-16f;
-    constexpr float ub = 0x1p-8f;
-    constexpr float kC1 = 1.25f * 2.0f * (2.0f * ub + ub * ub);
-    constexpr float kC2 = 1.25f * (DP + 8) * 0x1p-24f;
     const int lane = threadIdx.x & 63;
     const int wslot = threadIdx.x >> 6;
     const int n_list = a.q_n_leaves;
@@ -116,21 +108,7 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
     if (lane < DP) s_cen[lane] = 0.5f * (qb[lane] + qb[DP + lane]);
     wave_sync();
     bf16x8_t bq[S];
-    float qn = 0.f;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const float4 *cp = reinterpret_cast<const float4 *>(s_cen + s * 16 + h * 8);
-        const float4 *xp = reinterpret_cast<const float4 *>(a.qpts + int64_t(qpos) * DP + s * 16 + h * 8);
-        const float4 c0 = cp[0], c1 = cp[1], x0 = xp[0], x1 = xp[1];
-        const float cv[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-        const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float qd = valid ? xv[e] - cv[e] : 0.f;
-            qn = fmaf(qd, qd, qn);
-            bq[s][e] = (__bf16)(-2.0f * qd);
-        }
-    }
+    float qn = bf16_query_operand<DP>(a.qpts + int64_t(qpos) * DP, s_cen, h, valid, bq);
     qn = xor32_op(qn, OpAdd());
     const float qlen = sqrtf(qn);
     // leaf box for Score: lane l holds dimension l (0 beyond d, as stored)
@@ -207,32 +185,9 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
         const int islot = vr ? i : 0;  // rows past the leaf read slot 0 (in bounds)
         // reference operand: (r - c) in BF16, |r - c|^2 in FP32
         bf16x8_t ar[S];
-        float rn = 0.f;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const float4 *src = reinterpret_cast<const float4 *>(rp + islot * DP + s * 16 + h * 8);
-            const float4 *cp = reinterpret_cast<const float4 *>(s_cen + s * 16 + h * 8);
-            const float4 v0 = src[0], v1 = src[1], c0 = cp[0], c1 = cp[1];
-            const float rv[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-            const float cv[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float rd = vr ? rv[e] - cv[e] : 0.f;
-                rn = fmaf(rd, rd, rn);
-                ar[s][e] = (__bf16)rd;
-            }
-        }
+        float rn = bf16_ref_operand<DP>(rp + islot * DP, s_cen, h, vr, ar);
         rn = xor32_op(rn, OpAdd());
-        // largest norm of the tile: over each 16 rows by DPP, then the two
-        // halves on the scalar unit (non-negative floats order as unsigned
-        // integers)
-        const float r16 = reduce16(vr ? rn : 0.f, OpMax());
-        const float rmax = __builtin_bit_cast(
-            float, max((uint32_t)__builtin_amdgcn_readlane(__builtin_bit_cast(int, r16), 0),
-                       (uint32_t)__builtin_amdgcn_readlane(__builtin_bit_cast(int, r16), 16)));
-        // hardware square root (1 ulp), nudged up: the margin only needs an
-        // upper bound
-        const float rlen = __builtin_amdgcn_sqrtf(uniform_f(rmax)) * (1.0f + 0x1p-20f);
+        const float rlen = bf16_tile_rlen(rn, vr);  // largest |r'| of the tile
         if (h == 0) s_rn[i] = vr ? rn : kInf;
         wave_sync();
         f32x16_t acc;
@@ -244,12 +199,11 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
             acc[g4 * 4 + 2] = v.z;
             acc[g4 * 4 + 3] = v.w;
         }
-#pragma unroll
-        for (int s = 0; s < S; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[s], bq[s], acc, 0, 0, 0);
+        acc = bf16_tile_product<DP>(ar, bq, acc);
         wave_sync();  // s_rn is rewritten by the next tile
         // keep D <= T - |q'|^2 + M
         const float lim = fminf(pair_kth, bound2) * kSlack;
-        const float marg = kC1 * qlen * rlen + kC2 * (qlen + rlen) * (qlen + rlen);
+        const float marg = bf16_margin<DP>(qlen, rlen);
         const float thr = lim - qn + marg;
         // most tiles have no candidate at all: one test on the smallest value
         // of each lane skips the per-row mask, the survivor rounds and the

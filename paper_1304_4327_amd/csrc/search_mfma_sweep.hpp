@@ -68,9 +68,6 @@ k_search_mfma_sweep(const SearchArgs a) {
     constexpr int E = DP / 8;   // staged floats per thread (32 rows x DP / 256)
     constexpr float kInf = __builtin_inff();
     constexpr float kSlack = 1.0f + 0x1p-16f;
-    constexpr float ub = 0x1p-8f;
-    constexpr float kC1 = 1.25f * 2.0f * (2.0f * ub + ub * ub);
-    constexpr float kC2 = 1.25f * (DP + 8) * 0x1p-24f;
     __shared__ __align__(16) char smem[L::bytes];
     float *s_tf = reinterpret_cast<float *>(smem + L::off_tile_f);
     __bf16 *s_tb = reinterpret_cast<__bf16 *>(smem + L::off_tile_bf);
@@ -327,7 +324,7 @@ k_search_mfma_sweep(const SearchArgs a) {
         }
         // keep D <= T - |q'|^2 + M
         const float lim = fminf(pair_kth, bound2) * kSlack;
-        const float marg = kC1 * qlen * rlen + kC2 * (qlen + rlen) * (qlen + rlen);
+        const float marg = bf16_margin<DP>(qlen, rlen);
         const float thr = valid ? lim - qn + marg : -kInf;
         // most tiles have no candidate at all: one test on the smallest value
         // of each lane skips the per-row mask, the survivor rounds and the

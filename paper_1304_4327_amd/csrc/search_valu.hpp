@@ -71,7 +71,9 @@ __device__ inline double d2_fp64(const float (&q)[D], const float *r) {
     return s;
 }
 
-template <int D, int K, int LG>
+// DBG: the debug form (Score log, visit-order switch); the search kernels
+// are built with DBG = false, which compiles both out
+template <int D, int K, int LG, bool DBG = false>
 __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     constexpr int DP = stride_for(D);
     constexpr bool RESCORE = D > 8;
@@ -193,9 +195,34 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         key_out = uniform_f(u);
         return ballot(keep) != 0;
     };
+    // debug form: one record per Score call with each leaf's bound
+    auto log_score = [&](int node, bool keep) {
+        if constexpr (DBG) {
+            float bg[kDbgMaxLeaves];
+#pragma unroll
+            for (int g = 0; g < kDbgMaxLeaves; ++g)
+                bg[g] = g < NG ? __builtin_bit_cast(float, __builtin_amdgcn_readlane(
+                                                              __builtin_bit_cast(int, bound2), g << lpl_log2))
+                               : 0.f;
+            if (lane == 0) {
+                const unsigned r = atomicAdd(a.dbg_count, 1u);
+                if (int(r) < a.dbg_cap) {
+                    uint32_t *rec = a.dbg_log + int64_t(r) * kDbgWords;
+                    rec[0] = uint32_t(node);
+                    rec[1] = keep ? 1u : 0u;
+                    rec[2] = uint32_t(wave * NG);
+                    rec[3] = uint32_t(NG);
+#pragma unroll
+                    for (int g = 0; g < kDbgMaxLeaves; ++g) rec[4 + g] = __float_as_uint(bg[g]);
+                }
+            }
+        }
+    };
     auto score = [&](int node, float &key_out) -> bool {
         ++n_score;
-        return score_box(a.rbox + int64_t(node) * 2 * DP, key_out);
+        const bool keep = score_box(a.rbox + int64_t(node) * 2 * DP, key_out);
+        log_score(node, keep);
+        return keep;
     };
     // both children of an internal node: their boxes are adjacent
     auto score_children = [&](int c0, bool &k0, bool &k1, float &m0, float &m1) {
@@ -217,6 +244,8 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         }
         k0 = score_box(b, m0);
         k1 = score_box(b + 2 * DP, m1);
+        log_score(c0, k0);
+        log_score(c0 + 1, k1);
         tacc ^= q0 ^ q1 ^ q2;
         q0 = p0;
         q1 = p1;
@@ -375,7 +404,11 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
                             down = false;
                             continue;
                         }
-                        const bool right = k1 && (!k0 || dm1 < dm0);
+                        bool right = k1 && (!k0 || dm1 < dm0);
+                        if constexpr (DBG) {
+                            // farther child first: the other visit order
+                            if (a.far_first) right = k1 && (!k0 || dm1 > dm0);
+                        }
                         if (right)
                             nearbits |= (uint64_t(1) << depth);
                         else
@@ -462,13 +495,13 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     }
 }
 
-template <int D, int K>
+template <int D, int K, bool DBG = false>
 hipError_t launch_search_valu_k(const SearchArgs &a, int grid, hipStream_t s) {
     switch (a.lpl_log2) {
-        case 3: k_search_valu<D, K, 3><<<grid, 256, 0, s>>>(a); break;
-        case 4: k_search_valu<D, K, 4><<<grid, 256, 0, s>>>(a); break;
-        case 5: k_search_valu<D, K, 5><<<grid, 256, 0, s>>>(a); break;
-        case 6: k_search_valu<D, K, 6><<<grid, 256, 0, s>>>(a); break;
+        case 3: k_search_valu<D, K, 3, DBG><<<grid, 256, 0, s>>>(a); break;
+        case 4: k_search_valu<D, K, 4, DBG><<<grid, 256, 0, s>>>(a); break;
+        case 5: k_search_valu<D, K, 5, DBG><<<grid, 256, 0, s>>>(a); break;
+        case 6: k_search_valu<D, K, 6, DBG><<<grid, 256, 0, s>>>(a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

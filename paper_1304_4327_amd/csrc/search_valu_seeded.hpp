@@ -394,8 +394,11 @@ __global__ __launch_bounds__(256) void k_search_valu_seeded(const SearchArgs a) 
         }
         valid = fb_leaf;
         n_valid = __popcll(ballot(valid));
-        seed2 = kInf;
-        bound2 = (a.bound == KNN_BOUND_NONE || !fb_leaf) ? kInf : pb * pb;
+        // the proven bound stays in every refresh's minimum (as the seed
+        // term did in the first pass): the fresh lists give B1 = +inf until
+        // they fill
+        seed2 = (a.bound == KNN_BOUND_NONE || !fb_leaf) ? kInf : pb * pb;
+        bound2 = seed2;
     }
     valid = valid0;
 

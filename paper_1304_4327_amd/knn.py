@@ -103,6 +103,11 @@ _SIGS = {
     "knn_mlp_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_P)]),
     "knn_seed_features": (ctypes.c_int, [_P, _P, _P, _P]),
     "knn_seed_radius": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_float, _P, _P]),
+    "knn_debug_search_log": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts),
+                                            ctypes.c_int32, _P, ctypes.c_int64,
+                                            ctypes.POINTER(ctypes.c_int64), _P, _P, _P]),
+    "knn_debug_bf16_tiles": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P,
+                                            _P, _P]),
 }
 
 _lib = None
@@ -148,6 +153,45 @@ def _dev_f32(t, name):
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
     if t.dtype != torch.float32 or not t.is_contiguous() or t.dim() != 2:
         raise TypeError(f"{name} must be a contiguous 2-D float32 tensor")
+    return t
+
+
+def _n_leaves_for(n: int, leaf_size: int) -> int:
+    """Leaves of the tree the library builds over n points (complete tree of
+    the smallest depth L with ceil(n / 2^L) <= leaf_size)."""
+    L = 0
+    while -(-n // (1 << L)) > leaf_size:
+        L += 1
+    return 1 << L
+
+
+def _outputs(out, nq: int, k: int):
+    """(idx, dist) output tensors: new ones, or the caller's after checking
+    that the library may write n_q x k entries into them."""
+    torch = _torch()
+    if out is None:
+        return (torch.empty((nq, k), dtype=torch.int64, device="cuda"),
+                torch.empty((nq, k), dtype=torch.float32, device="cuda"))
+    idx, dist = out
+    for t, dt, nm in ((idx, torch.int64, "idx"), (dist, torch.float32, "dist")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise ValueError(f"out {nm} must be a CUDA (HIP) tensor")
+        if t.dtype != dt or not t.is_contiguous() or tuple(t.shape) != (nq, k):
+            raise ValueError(f"out {nm} must be a contiguous {dt} tensor of shape ({nq}, {k}), "
+                             f"got {t.dtype} {tuple(t.shape)}")
+    return idx, dist
+
+
+def _leaf_vec(t, n_leaves: int, name: str):
+    """A per-query-leaf float32 vector the library reads or writes."""
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n_leaves:
+        raise ValueError(f"{name} must be a contiguous float32 tensor with one entry per query "
+                         f"leaf ({n_leaves}), got {t.dtype} with {t.numel()} entries")
     return t
 
 
@@ -247,13 +291,13 @@ def knn_search(ref: Tree, query: Tree | None, k: int, bound="B", precision="fp32
     ``seed_radius``/``leaf_kth_out`` are CUDA float32 tensors with one entry
     per query leaf.
     """
-    torch = _torch()
-    nq = (query or ref).n
-    if out is None:
-        idx = torch.empty((nq, k), dtype=torch.int64, device="cuda")
-        dist = torch.empty((nq, k), dtype=torch.float32, device="cuda")
-    else:
-        idx, dist = out
+    qt = query or ref
+    nq = qt.n
+    idx, dist = _outputs(out, nq, k)
+    if seed_radius is not None or leaf_kth_out is not None:
+        nl = knn_tree_get_info(qt)["n_leaves"]
+        _leaf_vec(seed_radius, nl, "seed_radius")
+        _leaf_vec(leaf_kth_out, nl, "leaf_kth_out")
     o, st = _make_opts(bound, precision, exclude_self, seed_radius, leaf_kth_out, stats)
     _check(load().knn_search(ref.handle, query.handle if query is not None else None, int(k),
                              ctypes.byref(o), ctypes.c_void_p(idx.data_ptr()),
@@ -265,14 +309,13 @@ def knn_search_points(ref: Tree, queries, k: int, bound="B", precision="fp32",
                       seed_radius=None, leaf_kth_out=None, stats=False, out=None,
                       stream=None):
     """Build the query tree from ``queries`` (CUDA float32) and search."""
-    torch = _torch()
     _dev_f32(queries, "queries")
     nq = queries.shape[0]
-    if out is None:
-        idx = torch.empty((nq, k), dtype=torch.int64, device="cuda")
-        dist = torch.empty((nq, k), dtype=torch.float32, device="cuda")
-    else:
-        idx, dist = out
+    idx, dist = _outputs(out, nq, k)
+    if seed_radius is not None or leaf_kth_out is not None:
+        nl = _n_leaves_for(nq, knn_tree_get_info(ref)["leaf_size"])
+        _leaf_vec(seed_radius, nl, "seed_radius")
+        _leaf_vec(leaf_kth_out, nl, "leaf_kth_out")
     o, st = _make_opts(bound, precision, False, seed_radius, leaf_kth_out, stats)
     _check(load().knn_search_points(ref.handle, ctypes.c_void_p(queries.data_ptr()), nq,
                                     int(k), ctypes.byref(o), ctypes.c_void_p(idx.data_ptr()),
@@ -288,18 +331,13 @@ def knn_all_knn(ref_points, query_points, k: int, leaf_size: int, bound="B", pre
     Returns (idx int64 [n_q, k], dist float32 [n_q, k], stats dict or None);
     with stats, ``ms_ref_build``/``ms_query_build`` give the build times.
     """
-    torch = _torch()
     _dev_f32(ref_points, "ref_points")
     if query_points is not None:
         _dev_f32(query_points, "query_points")
         if query_points.shape[1] != ref_points.shape[1]:
             raise ValueError("ref_points and query_points differ in d")
     nq = (query_points if query_points is not None else ref_points).shape[0]
-    if out is None:
-        idx = torch.empty((nq, k), dtype=torch.int64, device="cuda")
-        dist = torch.empty((nq, k), dtype=torch.float32, device="cuda")
-    else:
-        idx, dist = out
+    idx, dist = _outputs(out, nq, k)
     o, st = _make_opts(bound, precision, exclude_self, None, None, stats)
     _check(load().knn_all_knn(ctypes.c_void_p(ref_points.data_ptr()), ref_points.shape[0],
                               ctypes.c_void_p(query_points.data_ptr()) if query_points is not None
@@ -436,3 +474,51 @@ def knn_seed_radius(mlp: Mlp, feats, log_margin: float = 0.0, stream=None):
                                   float(log_margin), ctypes.c_void_p(r.data_ptr()),
                                   _stream(stream)))
     return r
+
+
+# ---------------------------------------------------------------------------
+# test exports
+# ---------------------------------------------------------------------------
+def knn_debug_bf16_tiles(q, r, centre, stream=None):
+    """BF16 tiles as the matrix-core kernels compute them.  q, r: CUDA
+    float32 [n_tiles, 32, d]; centre: [n_tiles, d].  Returns (acc [n,32,32]
+    indexed [tile, ref row, query], qnorm [n,32], margin [n,32])."""
+    torch = _torch()
+    n, rows, d = q.shape
+    if rows != 32 or tuple(r.shape) != (n, 32, d) or tuple(centre.shape) != (n, d):
+        raise ValueError("need q, r of shape (n, 32, d) and centre of shape (n, d)")
+    for t, nm in ((q, "q"), (r, "r"), (centre, "centre")):
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError(f"{nm} must be a contiguous CUDA float32 tensor")
+    acc = torch.empty((n, 32, 32), dtype=torch.float32, device="cuda")
+    qn = torch.empty((n, 32), dtype=torch.float32, device="cuda")
+    mg = torch.empty((n, 32), dtype=torch.float32, device="cuda")
+    _check(load().knn_debug_bf16_tiles(ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(r.data_ptr()),
+                                       ctypes.c_void_p(centre.data_ptr()), n, d,
+                                       ctypes.c_void_p(acc.data_ptr()),
+                                       ctypes.c_void_p(qn.data_ptr()),
+                                       ctypes.c_void_p(mg.data_ptr()), _stream(stream)))
+    return acc, qn, mg
+
+
+DBG_WORDS = 12
+
+
+def knn_debug_search_log(ref: Tree, query: Tree | None, k: int, bound="B", exclude_self=False,
+                         far_first=False, capacity=1 << 20, stream=None):
+    """knn_search through the debug kernel (d = 3): returns (idx, dist, log
+    [n_records, 12] uint32 numpy, n_records).  The log holds one record per
+    Score call (see knn_debug_search_log in include/knn.h)."""
+    torch = _torch()
+    nq = (query or ref).n
+    idx, dist = _outputs(None, nq, k)
+    log = torch.zeros((max(1, capacity), DBG_WORDS), dtype=torch.int32, device="cuda")
+    n = ctypes.c_int64()
+    o, _ = _make_opts(bound, "fp32", exclude_self, None, None, False)
+    _check(load().knn_debug_search_log(ref.handle, query.handle if query is not None else None,
+                                       int(k), ctypes.byref(o), int(bool(far_first)),
+                                       ctypes.c_void_p(log.data_ptr()), int(capacity),
+                                       ctypes.byref(n), ctypes.c_void_p(idx.data_ptr()),
+                                       ctypes.c_void_p(dist.data_ptr()), _stream(stream)))
+    kept = min(n.value, capacity)
+    return idx, dist, log[:kept].cpu().numpy().view(np.uint32), n.value

@@ -99,3 +99,21 @@ def test_search_rejects_null_tree():
                         None)
     assert st == knn.KNN_E_INVALID_ARG
     assert b"NULL" in lib.knn_last_error()
+
+
+def test_binding_rejects_bad_output_and_leaf_tensors():
+    """The binding checks every buffer the library writes or reads by raw
+    pointer before the call (the C ABI cannot check device-buffer sizes)."""
+    import torch
+    cpu = torch.empty((4, 3), dtype=torch.int64)
+    with pytest.raises(ValueError):
+        knn._outputs((cpu, torch.empty((4, 3))), 4, 3)
+    with pytest.raises(ValueError):
+        knn._leaf_vec(torch.empty(8), 8, "seed_radius")
+    assert knn._leaf_vec(None, 8, "seed_radius") is None
+
+
+def test_leaf_count_rule():
+    from oracle import kdtree as kd
+    for n, leaf in [(1, 1), (5, 2), (10_000, 20), (1_000_000, 32), (262_144, 32), (33, 32)]:
+        assert knn._n_leaves_for(n, leaf) == 1 << kd.depth_for(n, leaf)

@@ -1,0 +1,93 @@
+"""The correctness argument of the k-NN Score checked on the GPU traversal
+itself, and the independence of the answer from the visit order.
+
+Section "k-Nearest Neighbor Search", after Algorithm 3: the bound B(N_q)
+never falls below the largest true k-th distance of a node's points, so a
+pruned node pair never holds a true neighbour.  The debug form of the d = 3
+FP32 kernel logs every Score call with each query leaf's bound; the log is
+checked against the oracle's answer (tests/_invariants.py).  Algorithm 4
+enters the closer reference child first; the answer must not depend on
+that choice, so the farther-first walk must return the same lists, bit for
+bit (equal distances are ordered by index)."""
+import numpy as np
+import pytest
+
+from oracle import knn as ok
+from oracle import parity
+from paper_1304_4327_amd import datagen
+
+from _invariants import check_log
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(ref, q, k, leaf, bound="B", far_first=False):
+    import torch
+    from paper_1304_4327_amd import knn
+    rt = knn.knn_build_tree(torch.from_numpy(ref).cuda(), leaf)
+    qt = None if q is None else knn.knn_build_tree(torch.from_numpy(q).cuda(), leaf)
+    idx, dist, log, n = knn.knn_debug_search_log(rt, qt, k, bound=bound, exclude_self=q is None,
+                                                 far_first=far_first, capacity=1 << 20)
+    ra = knn.tree_arrays(rt)
+    qa = ra if qt is None else knn.tree_arrays(qt)
+    if qt is not None:
+        qt.close()
+    rt.close()
+    return idx.cpu().numpy(), dist.cpu().numpy(), log, n, ra, qa
+
+
+def _check_invariants(ref, q, k, leaf, bound, far_first):
+    gi, gd, log, n, ra, qa = _run(ref, q, k, leaf, bound, far_first)
+    assert n == len(log), "log truncated"
+    qq = ref if q is None else q
+    oi, od = ok.knn(qq, ref, k, exclude_self=q is None)
+    parity.assert_ok(qq, ref, k, gi, gd, oi, od, exclude_self=q is None)
+    fq = qa["info"]["first_leaf"]
+    nl = qa["info"]["n_leaves"]
+    bb, pb, n_pruned = check_log(log, nl, ra["info"]["first_leaf"], qa["start"][fq:],
+                                 qa["count"][fq:], qa["perm"], ra["start"], ra["count"],
+                                 ra["perm"], oi, od, k)
+    print(f"{len(log)} Score calls, {n_pruned} pruned; bound violations {bb}, "
+          f"pruned pairs holding a true neighbour {pb}", flush=True)
+    assert bb == 0 and pb == 0
+    assert n_pruned > 0.1 * len(log)   # the bound does prune
+    return gi, gd, len(log)
+
+
+@pytest.mark.parametrize("bound", ["B", "B1"])
+@pytest.mark.parametrize("far_first", [False, True])
+def test_uniform10k_score_log(bound, far_first):
+    ref, _, k, leaf = datagen.make("uniform10k_d3_k5")
+    _check_invariants(ref, None, k, leaf, bound, far_first)
+
+
+def test_gmm_shape_score_log():
+    ref, q, k, leaf = datagen.make("gmm1m_d3_k10", scale=0.01)
+    _check_invariants(ref, q, k, leaf, "B", False)
+
+
+@pytest.mark.parametrize("name,scale", [("uniform10k_d3_k5", 1.0), ("gmm1m_d3_k10", 0.02)])
+def test_visit_order_does_not_change_the_answer(name, scale):
+    ref, q, k, leaf = datagen.make(name, scale=scale)
+    near = _run(ref, q, k, leaf, far_first=False)
+    far = _run(ref, q, k, leaf, far_first=True)
+    assert np.array_equal(near[0], far[0]) and np.array_equal(near[1], far[1])
+    assert near[3] != far[3]            # the two walks did differ
+    # the debug kernel returns what the search kernel returns
+    import torch
+    from paper_1304_4327_amd import knn
+    rt = knn.knn_build_tree(torch.from_numpy(ref).cuda(), leaf)
+    qt = None if q is None else knn.knn_build_tree(torch.from_numpy(q).cuda(), leaf)
+    idx, dist, _ = knn.knn_search(rt, qt, k, exclude_self=q is None)
+    assert np.array_equal(idx.cpu().numpy(), near[0])
+    assert np.array_equal(dist.cpu().numpy(), near[1])
+
+
+def test_debug_kernel_rejects_other_domains():
+    import torch
+    from paper_1304_4327_amd import knn
+    ref = datagen.uniform(1000, 4, 2)
+    rt = knn.knn_build_tree(torch.from_numpy(ref).cuda(), 16)
+    with pytest.raises(knn.KnnError) as e:
+        knn.knn_debug_search_log(rt, None, 5, exclude_self=True)
+    assert e.value.status == knn.KNN_E_UNSUPPORTED

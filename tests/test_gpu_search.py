@@ -259,3 +259,24 @@ def test_all_knn_rejects_k_too_large():
     with pytest.raises(knn.KnnError) as e:
         _all_knn(ref, qry, 50, 8)
     assert e.value.status == knn.KNN_E_INVALID_ARG
+
+
+def test_binding_rejects_wrong_output_shapes():
+    torch = _torch()
+    from paper_1304_4327_amd import knn
+    ref = datagen.uniform(500, 3, 4)
+    rt = knn.knn_build_tree(torch.from_numpy(ref).cuda(), 8)
+    nl = rt.info()["n_leaves"]
+    good = (torch.empty((500, 4), dtype=torch.int64, device="cuda"),
+            torch.empty((500, 4), dtype=torch.float32, device="cuda"))
+    for bad in [(good[0][:499], good[1]), (good[0], good[1].double()),
+                (good[0].t().contiguous().t(), good[1])]:
+        with pytest.raises(ValueError):
+            knn.knn_search(rt, None, 4, exclude_self=True, out=bad)
+    with pytest.raises(ValueError):
+        knn.knn_search(rt, None, 4, exclude_self=True,
+                       seed_radius=torch.zeros(nl - 1, device="cuda"))
+    with pytest.raises(ValueError):
+        knn.knn_search(rt, None, 4, exclude_self=True,
+                       leaf_kth_out=torch.zeros(nl, dtype=torch.float64, device="cuda"))
+    knn.knn_search(rt, None, 4, exclude_self=True, out=good)

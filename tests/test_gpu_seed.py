@@ -111,22 +111,46 @@ def _seeded(ref, q, k, leaf, seed_fn, precision="fp32"):
     return idx.cpu().numpy(), dist.cpu().numpy(), st
 
 
-@pytest.mark.parametrize("kind", ["zero", "inf", "random", "nan", "negative"])
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_any_seed_gives_the_plain_answer(kind, precision):
-    name = "zipfgmm2m_d8_k10" if precision == "fp32" else "manifold4m_d16_k10"
-    ref, q, k, leaf = datagen.make(name, scale=0.003)
-    plain = _seeded(ref, q, k, leaf, lambda n: None, precision)
+# seeds that send every leaf, some leaves or no leaf to the second pass;
+# "half" and "quarter" flag some of the leaves that share a wavefront (FP32
+# kernel) or a workgroup of four (d = 64 leaf sweep)
+def _seed_fn(kind, plain_dist):
     rng = np.random.default_rng(1)
-    fn = {"zero": lambda n: np.zeros(n), "inf": lambda n: np.full(n, np.inf),
-          "random": lambda n: rng.exponential(plain[1][:, -1].mean(), n),
-          "nan": lambda n: np.full(n, np.nan), "negative": lambda n: -np.ones(n)}[kind]
-    got = _seeded(ref, q, k, leaf, fn, precision)
+    mean_kth = float(plain_dist[:, -1].mean())
+    return {"zero": lambda n: np.zeros(n), "inf": lambda n: np.full(n, np.inf),
+            "random": lambda n: rng.exponential(mean_kth, n),
+            "half": lambda n: np.where(np.arange(n) % 2 == 0, np.inf, 0.0),
+            "quarter": lambda n: np.where(np.arange(n) % 4 == 3, 0.0, np.inf),
+            "nan": lambda n: np.full(n, np.nan), "negative": lambda n: -np.ones(n)}[kind]
+
+
+@pytest.mark.parametrize("kind", ["zero", "inf", "random", "half", "quarter", "nan", "negative"])
+@pytest.mark.parametrize("name,precision,scale", [("zipfgmm2m_d8_k10", "fp32", 0.003),
+                                                  ("manifold4m_d16_k10", "bf16", 0.003),
+                                                  ("manifold1m_d64_k50", "bf16", 0.01)])
+def test_any_seed_gives_the_oracle_answer(kind, name, precision, scale):
+    """Any seed keeps the answer exact: leaves whose queries end beyond
+    their seed are searched again (the FP32 kernel's in-wave second pass,
+    the BF16 kernels' second launch) and must still match the oracle, and
+    equal the plain search bit for bit."""
+    ref, q, k, leaf = datagen.make(name, scale=scale)
+    print(f"seed {kind}: {name} {precision} n_ref={len(ref)} n_q={len(q)}", flush=True)
+    plain = _seeded(ref, q, k, leaf, lambda n: None, precision)
+    got = _seeded(ref, q, k, leaf, _seed_fn(kind, plain[1]), precision)
+    oi, od = ok.knn(q, ref, k)
+    parity.assert_ok(q, ref, k, got[0], got[1], oi, od)
     assert np.array_equal(got[0], plain[0]) and np.array_equal(got[1], plain[1])
+    st, nl = got[2], got[2]["n_query_leaves"]
     if kind in ("zero", "nan", "negative"):
-        assert got[2]["fallback_leaves"] == got[2]["n_query_leaves"]
-    if kind == "inf":
-        assert got[2]["fallback_leaves"] == 0
+        assert st["fallback_leaves"] == nl
+    elif kind == "inf":
+        assert st["fallback_leaves"] == 0
+    elif kind == "half":
+        assert st["fallback_leaves"] == nl // 2
+    elif kind == "quarter":
+        assert st["fallback_leaves"] == nl // 4
+    else:
+        assert 0 < st["fallback_leaves"] < nl
 
 
 def test_trained_seed_prunes_more_and_stays_exact():
