@@ -207,3 +207,83 @@ def printed_bound_bottom_up(tree, kth):
                                  for x in kids if tree["count"][x] > 0]
             printed[node] = min(terms)
     return printed, safe, need
+
+
+class DualTreeKFN(DualTreeKNN):
+    """Literal k-furthest-neighbour dual-tree search (the closing remark of
+    Section "k-Nearest Neighbor Search"): the k-NN rules with max and min
+    exchanged, lists kept in descending distance, D initialised to 0 and the
+    BaseCase comparison d > D[k].
+
+    Inverted bound (safe reading, the mirror of the k-NN one): every point
+    p of N_q ends with a k-th furthest distance of at least
+      L1 = min over the node's points of D_p[k]  (the list only grows), and
+      L2 = max over the node's points of D_p[k] - 2 lambda(N_q) (the k points
+           found for that point are, by the triangle inequality, at least
+           that far from every point of the node), and the parent's L,
+    so L(N_q) = max{L1, L2, L(Par)}, and a pair whose largest possible
+    distance d_max(N_q, N_r) is below L cannot change any list: Score prunes
+    iff d_max < L.  ``bound`` is "B" (all three terms), "B1" (L1 and the
+    parent) or "none"."""
+
+    def __init__(self, qpts, rpts, k, leaf_size=2, bound="B", exclude_self=False):
+        super().__init__(qpts, rpts, k, leaf_size, bound, exclude_self)
+        self.D = np.zeros_like(self.D)          # initialised to 0
+
+    def _dmax(self, nq, nr):
+        tq, tr = self.tq, self.tr
+        if tq["count"][nq] == 0 or tr["count"][nr] == 0:
+            return -math.inf
+        lo_q, hi_q = tq["lo"][nq].astype(np.float64), tq["hi"][nq].astype(np.float64)
+        lo_r, hi_r = tr["lo"][nr].astype(np.float64), tr["hi"][nr].astype(np.float64)
+        span = np.maximum(hi_r - lo_q, hi_q - lo_r)
+        return float(np.sqrt((span * span).sum()))
+
+    def _L(self, node):
+        pts = self._kth(node)
+        if pts.size == 0:
+            return -math.inf
+        b = pts.min()
+        if self.bound == "B":
+            b = max(b, pts.max() - 2.0 * self.tq["lam"][node])
+        if node > 0:
+            b = max(b, self._L((node - 1) // 2))
+        return b
+
+    def score(self, nq, nr):
+        self.score_calls += 1
+        dmax = self._dmax(nq, nr)
+        if self.bound != "none" and dmax < self._L(nq):
+            return math.inf
+        return -dmax                         # larger d_max visited first
+
+    def base_case(self, iq, ir):
+        if self.exclude_self and iq == ir:
+            return 0.0
+        self.base_cases += 1
+        diff = self.q[iq] - self.r[ir]
+        d = math.sqrt(float(diff @ diff))
+        if d > self.D[iq, self.k - 1] and (iq, ir) not in self.visited:
+            self.visited.add((iq, ir))
+            row_d, row_n = self.D[iq], self.N[iq]
+            pos = int(np.searchsorted(-row_d, -d, side="right"))
+            row_d[pos + 1:] = row_d[pos:-1].copy()
+            row_n[pos + 1:] = row_n[pos:-1].copy()
+            row_d[pos], row_n[pos] = d, ir
+        return d
+
+    def traverse(self, nq=0, nr=0):
+        if self.score(nq, nr) == math.inf:
+            return
+        for iq in self._held(self.tq, nq):
+            for ir in self._held(self.tr, nr):
+                self.base_case(int(iq), int(ir))
+        cq = self._children(self.tq, nq) or [nq]
+        cr = self._children(self.tr, nr) or [nr]
+        if cq == [nq] and cr == [nr]:
+            return
+        for c in cq:
+            # farther reference child first
+            order = sorted(cr, key=lambda x: -self._dmax(c, x))
+            for x in order:
+                self.traverse(c, x)

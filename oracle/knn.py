@@ -39,6 +39,8 @@ def _load():
         lib.knn_oracle_pair_d2.argtypes = [p, p, i32, p, p, i64, p]
         lib.knn_oracle_pair_d2.restype = ctypes.c_int
         lib.knn_oracle_threads.restype = ctypes.c_int
+        lib.knn_oracle_furthest_rows.argtypes = [p, p, i64, p, i64, i32, i32, i32, p, p]
+        lib.knn_oracle_furthest_rows.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -107,4 +109,42 @@ def knn_numpy(q, r, k: int, exclude_self: bool = False):
     if exclude_self:
         np.fill_diagonal(d2, np.inf)
     order = np.argsort(d2, axis=1, kind="stable")[:, :k]
+    return order.astype(np.int64), np.take_along_axis(d2, order, axis=1)
+
+
+# --------------------------------------------------------------------------
+# k-furthest neighbours (closing remark of Section "k-Nearest Neighbor
+# Search"): the k references at the largest distances, descending; equal
+# distances by reference index.
+# --------------------------------------------------------------------------
+def furthest_rows(q, rows, r, k: int, exclude_self: bool = False):
+    """Queries ``q[rows]`` only.  Returns (idx int64 [len(rows), k], d2
+    float64), distances descending."""
+    q, r = _f32(q), _f32(r)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    idx = np.empty((len(rows), k), np.int64)
+    d2 = np.empty((len(rows), k), np.float64)
+    rc = _load().knn_oracle_furthest_rows(q.ctypes.data, rows.ctypes.data, len(rows),
+                                          r.ctypes.data, r.shape[0], q.shape[1], k,
+                                          int(bool(exclude_self)), idx.ctypes.data,
+                                          d2.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle: invalid arguments (need 0 < k < m)")
+    return idx, d2
+
+
+def furthest(q, r, k: int, exclude_self: bool = False):
+    return furthest_rows(q, np.arange(len(q)), r, k, exclude_self)
+
+
+def furthest_numpy(q, r, k: int, exclude_self: bool = False):
+    """The same definition in numpy (tiny inputs): a stable sort on
+    (-distance, index)."""
+    q = np.asarray(q, np.float32).astype(np.float64)
+    r = np.asarray(r, np.float32).astype(np.float64)
+    diff = q[:, None, :] - r[None, :, :]
+    d2 = np.einsum("ijk,ijk->ij", diff, diff)
+    if exclude_self:
+        np.fill_diagonal(d2, -np.inf)
+    order = np.argsort(-d2, axis=1, kind="stable")[:, :k]
     return order.astype(np.int64), np.take_along_axis(d2, order, axis=1)

@@ -156,3 +156,54 @@ int knn_oracle_pair_d2(const float *q, const float *r, int32_t d,
     }
     return 0;
 }
+
+/*
+ * k-furthest neighbours (the closing remark of Section "k-Nearest Neighbor
+ * Search": the same problem with the order reversed): for each selected
+ * query the k references at the LARGEST distances, in descending order of
+ * distance; equal distances are ordered by reference index (lower first).
+ * exclude_self as above.  Same argument conventions as
+ * knn_oracle_bruteforce_rows; d2_out holds squared FP64 distances.
+ */
+static int after(double da, int64_t ia, double db, int64_t ib)
+{
+    return (da > db) || (da == db && ia < ib);
+}
+
+int knn_oracle_furthest_rows(const float *q, const int64_t *qsel, int64_t nsel,
+                             const float *r, int64_t m, int32_t d, int32_t k,
+                             int32_t exclude_self, int64_t *idx_out, double *d2_out)
+{
+    if (!q || !qsel || !r || !idx_out || !d2_out || nsel < 0 || m <= 0 || d <= 0 ||
+        k <= 0 || k >= m)
+        return -1;
+    int64_t t;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (t = 0; t < nsel; ++t) {
+        int64_t i = qsel[t];
+        double *bd = d2_out + t * (int64_t)k;
+        int64_t *bi = idx_out + t * (int64_t)k;
+        int len = 0;
+        const float *qi = q + i * (int64_t)d;
+        for (int64_t j = 0; j < m; ++j) {
+            if (exclude_self && j == i) continue;
+            const float *rj = r + j * (int64_t)d;
+            double s = 0.0;
+            for (int u = 0; u < d; ++u) {
+                double diff = (double)qi[u] - (double)rj[u];
+                s += diff * diff;
+            }
+            if (len == k && !after(s, j, bd[k - 1], bi[k - 1])) continue;
+            int pos = (len < k) ? len : k - 1;
+            while (pos > 0 && after(s, j, bd[pos - 1], bi[pos - 1])) {
+                bd[pos] = bd[pos - 1];
+                bi[pos] = bi[pos - 1];
+                --pos;
+            }
+            bd[pos] = s;
+            bi[pos] = j;
+            if (len < k) ++len;
+        }
+    }
+    return 0;
+}

@@ -93,3 +93,53 @@ def assert_ok(*args, **kw):
     bad = {k: v for k, v in fails.items() if v}
     assert not bad, f"parity failures {bad} ({info})"
     return info
+
+
+def check_furthest(q, r, k, gpu_idx, gpu_dist, ora_idx, ora_d2, rows=None,
+                   exclude_self=False, tol_set=TOL_SET, tol_dist=TOL_DIST):
+    """The same predicate for k-furthest lists (descending distances):
+    {r : delta_r > delta_k (1 + tol_set)} is a subset of G, G is a subset of
+    {r : delta_r >= delta_k (1 - tol_set)}, distances within tol_dist of
+    FP64 and non-increasing.  Returns (failure counts, info)."""
+    q = np.asarray(q, np.float32)
+    r = np.asarray(r, np.float32)
+    m = r.shape[0]
+    rows = np.arange(q.shape[0]) if rows is None else np.asarray(rows, np.int64)
+    gi = np.asarray(gpu_idx)[rows].astype(np.int64)
+    gd = np.asarray(gpu_dist)[rows].astype(np.float64)
+    oi = np.asarray(ora_idx, np.int64)
+    od2 = np.asarray(ora_d2, np.float64)
+    assert gi.shape == (len(rows), k) and oi.shape == gi.shape
+
+    fails = {}
+    in_range = (gi >= 0) & (gi < m)
+    fails["out_of_range"] = int((~in_range).sum())
+    gi_safe = np.where(in_range, gi, 0)
+    srt = np.sort(gi_safe, axis=1)
+    fails["duplicates"] = int((srt[:, 1:] == srt[:, :-1]).any(axis=1).sum()) if k > 1 else 0
+    fails["self_match"] = int((gi == rows[:, None]).any(axis=1).sum()) if exclude_self else 0
+    qi = np.repeat(rows, k)
+    delta_g = np.sqrt(_knn.pair_d2(q, r, qi, gi_safe.ravel()).reshape(len(rows), k))
+    delta_o = np.sqrt(od2)
+    dk = delta_o[:, k - 1:k]
+    lower = delta_g >= dk * (1.0 - tol_set)
+    fails["beyond_kth"] = int((~lower & in_range).any(axis=1).sum())
+    must = delta_o > dk * (1.0 + tol_set)
+    missing = np.zeros(len(rows), bool)
+    for j in range(k):
+        present = (gi == oi[:, j:j + 1]).any(axis=1)
+        missing |= must[:, j] & ~present
+    fails["missing_neighbour"] = int(missing.sum())
+    err = np.abs(gd - delta_g)
+    bad = (err > tol_dist * delta_g) | ((delta_g == 0) & (gd != 0))
+    fails["distance_error"] = int((bad & in_range).any(axis=1).sum())
+    fails["unsorted"] = int((np.diff(gd, axis=1) > 0).any(axis=1).sum()) if k > 1 else 0
+    exact_sets = (np.sort(gi, axis=1) == np.sort(oi, axis=1)).all(axis=1)
+    return fails, {"rows": len(rows), "identical_sets": int(exact_sets.sum())}
+
+
+def assert_ok_furthest(*args, **kw):
+    fails, info = check_furthest(*args, **kw)
+    bad = {a: b for a, b in fails.items() if b}
+    assert not bad, f"parity failures {bad} ({info})"
+    return info
