@@ -198,6 +198,25 @@ knn_status knn_search(const knn_tree *ref, const knn_tree *query, int32_t k,
                       const knn_opts *opts, int64_t *idx_out, float *dist_out,
                       void *stream);
 
+/* knn_search for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same search, kernels and answer as knn_search on trees built beforehand,
+ * with the per-call scratch (launch order, counters, fallback flags and
+ * bounds) in a fixed 4 MiB device array that the library holds on every
+ * device it runs on until the process ends.  It calls no device allocation
+ * or free and records no memset node (clears are kernels).  Limits: query
+ * trees of up to 2^18 leaves always fit; a larger tree whose scratch
+ * (12 bytes per query leaf with a seed, 4 per wavefront of leaves without)
+ * exceeds the array is rejected with KNN_E_INVALID_ARG before any device
+ * work; the trees must belong to the current device.  Every call on a device shares that device's array, so
+ * calls that overlap on one device (other threads, other streams) race and
+ * must be serialised by the caller.  With opts->stats the counters are
+ * filled and the ms_* timing fields are 0 (no events are created).  Other
+ * arguments, errors and outputs as knn_search. */
+knn_status knn_search_noalloc(const knn_tree *ref, const knn_tree *query, int32_t k,
+                              const knn_opts *opts, int64_t *idx_out, float *dist_out,
+                              void *stream);
+
 /* Convenience: builds the query tree from `queries` (device, n_q x d) with
  * the reference tree's leaf size, searches, frees it.  The query-tree build
  * time is reported in stats->ms_query_build. */

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 namespace knnx {
@@ -26,6 +27,18 @@ knn_status hip_fail(hipError_t e, const char *what, const char *file, int line) 
                     std::to_string(line) + ")";
     set_error(m);
     return e == hipErrorOutOfMemory ? KNN_E_OOM : KNN_E_DEVICE;
+}
+
+// zero n 32-bit words (a kernel rather than a memset node: callers may
+// capture the search in a graph)
+__global__ void k_zero_words(uint32_t *__restrict__ p, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+hipError_t zero_words(void *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_zero_words<<<int((n + 255) / 256), 256, 0, s>>>(static_cast<uint32_t *>(p), n);
+    return hipGetLastError();
 }
 
 namespace {
@@ -104,17 +117,30 @@ __global__ __launch_bounds__(1024) void k_order(const float *__restrict__ lam, i
         order[atomicAdd(&cnt[order_bucket(lam, first_leaf, n_leaves, ng, w)], 1)] = w;
 }
 
+// Per-call scratch: blocks from the caching allocator, or consecutive
+// 256-byte aligned pieces of a fixed arena (the no-alloc entry point; its
+// size is checked before any device work)
 struct Scratch {
     hipStream_t s;
     std::vector<void *> p;
+    const ScratchArena *arena = nullptr;
+    size_t used = 0;
+    static size_t piece(size_t bytes) { return (bytes + 255) & ~size_t(255); }
     template <class T>
     hipError_t get(T **out, size_t n) {
+        if (arena) {
+            const size_t b = piece(n * sizeof(T));
+            if (used + b > arena->bytes) return hipErrorOutOfMemory;
+            *out = reinterpret_cast<T *>(arena->base + used);
+            used += b;
+            return hipSuccess;
+        }
         hipError_t e = alloc_async(out, n, s);
         if (e == hipSuccess) p.push_back(*out);
         return e;
     }
     ~Scratch() {
-        dev_free_many(p.data(), int(p.size()), s);
+        if (!arena) dev_free_many(p.data(), int(p.size()), s);
     }
 };
 
@@ -126,7 +152,8 @@ knn_status validate_tree(const knn_tree *t, const char *who) {
 }  // namespace
 
 knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_opts *opts_in,
-                  int64_t *idx_out, float *dist_out, hipStream_t s, DebugReq *dbg) {
+                  int64_t *idx_out, float *dist_out, hipStream_t s, DebugReq *dbg,
+                  const ScratchArena *arena) {
     KNN_TRY(validate_tree(ref, "knn_search"));
     knn_opts opts;
     knn_opts_default(&opts);
@@ -169,17 +196,32 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
                     "knn_debug_search_log: the debug kernel covers d = 3, FP32, no seed, "
                     "lists of at most 16");
 
-    Scratch sc{s, {}};
+    const int waves = (nq_leaves + NG - 1) / NG;
+    const int grid = (waves + 3) / 4;
+    const bool use_order = (!bf16 || ref->dp < 64) && waves > 1;
+    if (arena) {
+        const size_t need = Scratch::piece(2 * ST_COUNT * sizeof(unsigned long long)) +
+                            (opts.seed_radius ? Scratch::piece(size_t(nq_leaves) * 4) +
+                                                    Scratch::piece(size_t(nq_leaves + 1) * 4)
+                                              : 0) +
+                            (use_order ? Scratch::piece(size_t(waves) * 4) : 0);
+        if (dbg || need > arena->bytes)
+            return fail(KNN_E_INVALID_ARG,
+                        "knn_search_noalloc: the query tree needs " + std::to_string(need) +
+                            " bytes of scratch, more than the fixed " +
+                            std::to_string(arena->bytes));
+    }
+
+    Scratch sc{s, {}, arena};
     unsigned long long *dstats = nullptr;
     if (opts.stats) KNN_HIP(sc.get(&dstats, 2 * ST_COUNT));  // cleared before the launch
     int *fb_flag = nullptr, *fb_count = nullptr;
     float *fb_bound = nullptr;
     if (opts.seed_radius) {
         KNN_HIP(sc.get(&fb_bound, nq_leaves));
-        KNN_HIP(sc.get(&fb_flag, nq_leaves));
-        KNN_HIP(sc.get(&fb_count, 1));
-        KNN_HIP(hipMemsetAsync(fb_flag, 0, nq_leaves * sizeof(int), s));
-        KNN_HIP(hipMemsetAsync(fb_count, 0, sizeof(int), s));
+        KNN_HIP(sc.get(&fb_flag, nq_leaves + 1));  // the flags, then their count
+        fb_count = fb_flag + nq_leaves;
+        KNN_HIP(zero_words(fb_flag, nq_leaves + 1, s));
     }
 
     SearchArgs a{};
@@ -211,49 +253,52 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     a.fb_bound = fb_bound;
     a.stats = dstats;
     // debug aid: KNN_WAVE_LOG=<file> writes per-wave counters of the main launch
-    const char *wlog_path = std::getenv("KNN_WAVE_LOG");
+    const char *wlog_path = arena ? nullptr : std::getenv("KNN_WAVE_LOG");
     uint32_t *wlog = nullptr;
 
     if (dbg) {
         unsigned int *cnt = nullptr;
         KNN_HIP(sc.get(&cnt, 1));
-        KNN_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned int), s));
+        KNN_HIP(zero_words(cnt, 1, s));
         a.dbg_log = dbg->log;
         a.dbg_count = cnt;
         a.dbg_cap = int(std::min<int64_t>(dbg->cap, INT32_MAX));
         a.far_first = dbg->far_first;
     }
-    const int waves = (nq_leaves + NG - 1) / NG;
-    const int grid = (waves + 3) / 4;
     if (wlog_path) {
         KNN_HIP(sc.get(&wlog, size_t(grid) * 4 * 8));
-        KNN_HIP(hipMemsetAsync(wlog, 0, size_t(grid) * 32 * sizeof(uint32_t), s));
+        KNN_HIP(zero_words(wlog, int64_t(grid) * 32, s));
         a.wave_log = wlog;
     }
     // (the stride-64 BF16 kernel sweeps reference leaves per workgroup of
     // four query leaves and takes no order)
-    if ((!bf16 || ref->dp < 64) && waves > 1) {
+    if (use_order) {
         int *order = nullptr;
         KNN_HIP(sc.get(&order, waves));
         k_order<<<1, 1024, 0, s>>>(qt->lam, int(qt->first_leaf), nq_leaves, NG, waves, order,
                                    dstats, dstats ? 2 * ST_COUNT : 0);
         a.order = order;
     } else if (dstats) {
-        KNN_HIP(hipMemsetAsync(dstats, 0, 2 * ST_COUNT * sizeof(unsigned long long), s));
+        KNN_HIP(zero_words(dstats, 2 * 2 * ST_COUNT, s));
     }
-    hipEvent_t ev[4];
-    for (auto &e : ev) KNN_HIP(hipEventCreate(&e));
+    // device timing (not in the no-alloc form: it creates no events)
+    hipEvent_t ev[4] = {};
     struct EvGuard {
         hipEvent_t *e;
         ~EvGuard() {
-            for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+            for (int i = 0; i < 4; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
         }
     } eg{ev};
-    KNN_HIP(hipEventRecord(ev[0], s));
+    const bool timing = opts.stats && !arena;
+    if (timing) {
+        for (auto &e : ev) KNN_HIP(hipEventCreate(&e));
+        KNN_HIP(hipEventRecord(ev[0], s));
+    }
     KNN_HIP(dbg    ? launch_search_valu_debug_d3(a, K, grid, s)
             : bf16 ? launch_mfma(a, ref->dp, K, grid, s)
                    : launch_valu(a, ref->d, K, grid, s));
-    KNN_HIP(hipEventRecord(ev[1], s));
+    if (timing) KNN_HIP(hipEventRecord(ev[1], s));
     if (opts.seed_radius) {
         k_count_flags<<<(nq_leaves + 255) / 256, 256, 0, s>>>(fb_flag, nq_leaves, fb_count);
     }
@@ -270,7 +315,7 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
         b.wave_log = nullptr;
         KNN_HIP(launch_mfma(b, ref->dp, K, grid, s));
     }
-    KNN_HIP(hipEventRecord(ev[2], s));
+    if (timing) KNN_HIP(hipEventRecord(ev[2], s));
     unsigned long long hst[2 * ST_COUNT] = {};
     int hfb = 0;
     if (dstats)
@@ -299,10 +344,38 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
         st->fallback_queries = int64_t(hst[ST_FB_QUERIES]);
         st->fallback_pairs = int64_t(f[ST_PAIRS]);
         st->fallback_leaves = hfb;
-        (void)hipEventElapsedTime(&st->ms_main_kernel, ev[0], ev[1]);
-        (void)hipEventElapsedTime(&st->ms_search, ev[0], ev[2]);
+        st->ms_main_kernel = st->ms_search = 0.f;
+        if (timing) {
+            (void)hipEventElapsedTime(&st->ms_main_kernel, ev[0], ev[1]);
+            (void)hipEventElapsedTime(&st->ms_search, ev[0], ev[2]);
+        }
         st->n_query_leaves = nq_leaves;
     }
+    return KNN_OK;
+}
+
+// Scratch of knn_search_noalloc: one fixed array per device, resolved to
+// its device address once per device (host code never uses the array's
+// name as an address).  Calls that overlap on one device share it.
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+knn_status noalloc_arena(ScratchArena *out) {
+    int dev = 0;
+    KNN_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(KNN_E_UNSUPPORTED, "knn_search_noalloc: device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+        g_scratch_ptr[dev] = static_cast<char *>(p);
+    }
+    *out = ScratchArena{g_scratch_ptr[dev], kNoAllocScratchBytes};
     return KNN_OK;
 }
 
@@ -415,6 +488,21 @@ knn_status knn_search(const knn_tree *ref, const knn_tree *query, int32_t k,
                       const knn_opts *opts, int64_t *idx_out, float *dist_out, void *stream) {
     set_error("");
     return search(ref, query, k, opts, idx_out, dist_out, (hipStream_t)stream);
+}
+
+knn_status knn_search_noalloc(const knn_tree *ref, const knn_tree *query, int32_t k,
+                              const knn_opts *opts, int64_t *idx_out, float *dist_out,
+                              void *stream) {
+    set_error("");
+    KNN_TRY(validate_tree(ref, "knn_search_noalloc"));
+    int dev = 0;
+    KNN_HIP(hipGetDevice(&dev));
+    if (ref->device != dev || (query && query->device != dev))
+        return fail(KNN_E_INVALID_ARG,
+                    "knn_search_noalloc: the trees belong to another device than the current one");
+    ScratchArena arena{};
+    KNN_TRY(noalloc_arena(&arena));
+    return search(ref, query, k, opts, idx_out, dist_out, (hipStream_t)stream, nullptr, &arena);
 }
 
 knn_status knn_debug_search_log(const knn_tree *ref, const knn_tree *query, int32_t k,

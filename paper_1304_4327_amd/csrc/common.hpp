@@ -166,9 +166,16 @@ struct DebugReq {
     int64_t cap;
     int64_t n_records;   // out: records the kernel produced (may exceed cap)
 };
+// a fixed device region the search takes its scratch from instead of the
+// allocator (knn_search_noalloc)
+struct ScratchArena {
+    char *base;
+    size_t bytes;
+};
 // the search of an existing pair of trees (api.hip)
 knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_opts *opts,
-                  int64_t *idx_out, float *dist_out, hipStream_t s, DebugReq *dbg = nullptr);
+                  int64_t *idx_out, float *dist_out, hipStream_t s, DebugReq *dbg = nullptr,
+                  const ScratchArena *arena = nullptr);
 
 // Device memory for trees and scratch comes from the library's caching
 // allocator (memory.hip): stream-ordered reuse of released blocks.

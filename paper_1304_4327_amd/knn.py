@@ -103,6 +103,8 @@ _SIGS = {
     "knn_mlp_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_P)]),
     "knn_seed_features": (ctypes.c_int, [_P, _P, _P, _P]),
     "knn_seed_radius": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_float, _P, _P]),
+    "knn_search_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts), _P,
+                                          _P, _P]),
     "knn_debug_search_log": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts),
                                             ctypes.c_int32, _P, ctypes.c_int64,
                                             ctypes.POINTER(ctypes.c_int64), _P, _P, _P]),
@@ -302,6 +304,24 @@ def knn_search(ref: Tree, query: Tree | None, k: int, bound="B", precision="fp32
     _check(load().knn_search(ref.handle, query.handle if query is not None else None, int(k),
                              ctypes.byref(o), ctypes.c_void_p(idx.data_ptr()),
                              ctypes.c_void_p(dist.data_ptr()), _stream(stream)))
+    return idx, dist, _stats_dict(st)
+
+
+def knn_search_noalloc(ref: Tree, query: Tree | None, k: int, out, bound="B", precision="fp32",
+                       exclude_self=False, seed_radius=None, stats=False, stream=None):
+    """knn_search without device allocation: the caller passes the outputs
+    (idx int64 [n_q, k], dist float32 [n_q, k]); the library's scratch is a
+    fixed per-device array (query trees of up to 2^18 leaves)."""
+    if out is None:
+        raise ValueError("knn_search_noalloc needs caller-allocated outputs (out=(idx, dist))")
+    qt = query or ref
+    idx, dist = _outputs(out, qt.n, k)
+    if seed_radius is not None:
+        _leaf_vec(seed_radius, knn_tree_get_info(qt)["n_leaves"], "seed_radius")
+    o, st = _make_opts(bound, precision, exclude_self, seed_radius, None, stats)
+    _check(load().knn_search_noalloc(ref.handle, query.handle if query is not None else None,
+                                     int(k), ctypes.byref(o), ctypes.c_void_p(idx.data_ptr()),
+                                     ctypes.c_void_p(dist.data_ptr()), _stream(stream)))
     return idx, dist, _stats_dict(st)
 
 
