@@ -166,6 +166,7 @@ def combined(args):
     model = S.train_for_workload(name, seeds, epochs=args.train_epochs, precision="bf16",
                                  target_fallback=args.target_fallback)
     train_s = time.perf_counter() - t0
+    print(f"combined: seed network trained in {train_s:.1f} s", file=sys.stderr, flush=True)
 
     def plain(precision, bound="B"):
         return lambda: knn.knn_all_knn(R, Q, k, leaf, bound=bound, precision=precision,
@@ -194,6 +195,7 @@ def combined(args):
             res[key]["fallback_leaves"] = float(np.mean([s["fallback_leaves"] for s in sts]))
             res[key]["query_leaves"] = sts[0]["n_query_leaves"]
         answers[key] = (outs[-1][0].cpu().numpy(), outs[-1][1].cpu().numpy())
+        print(f"combined: {key} {ms:.2f} ms/step", file=sys.stderr, flush=True)
     line = {"workload": name, "n_ref": len(ref), "n_query": nq, "d": ref.shape[1], "k": k,
             "baseline": "plain FP32 dual-tree traversal, bound B",
             "speedup_learned_bf16_vs_plain_fp32":

@@ -240,6 +240,28 @@ knn_status knn_all_knn(const float *ref_points, int64_t n_ref, const float *quer
                        const knn_opts *opts, int64_t *idx_out, float *dist_out, void *stream);
 
 
+/* k-furthest neighbours (the closing remark of Section "k-Nearest Neighbor
+ * Search": the same meta-algorithm with the bound inverted -- max and min
+ * exchanged -- lists in descending distance and the BaseCase comparison
+ * d > D_p[k]).  For every query point the k reference points at the
+ * LARGEST distances.  The bound is L(N_q) = max{ min_p D_p[k],
+ * max_p D_p[k] - 2 lambda(N_q), L(Par(N_q)) }, a lower bound on every
+ * point's final k-th farthest distance, and Score prunes a node whose box
+ * lies entirely nearer than it (strictly, with a 2^-16 relative slack).
+ * opts: bound (KNN_BOUND_B all three terms, KNN_BOUND_B1 the first and the
+ * parent's, KNN_BOUND_NONE no pruning), exclude_self, stats; precision must
+ * be FP32 and seed_radius, leaf_kth_out NULL (else KNN_E_UNSUPPORTED).
+ * Outputs (device, n_q x k, original query order): idx_out = original
+ * reference row, dist_out = FP32 of the FP64 distance, DESCENDING; equal
+ * distances are ordered by reference index.  Lists start empty (the paper
+ * starts them at distance 0), so a reference at distance 0 from the query
+ * (a duplicate) is still returned when fewer than k others are farther.
+ * Domain as knn_search (1 <= k <= 64, k < m; k <= 63 with exclude_self).
+ * Errors: KNN_E_INVALID_ARG, KNN_E_UNSUPPORTED, KNN_E_OOM, KNN_E_DEVICE. */
+knn_status knn_search_furthest(const knn_tree *ref, const knn_tree *query, int32_t k,
+                               const knn_opts *opts, int64_t *idx_out, float *dist_out,
+                               void *stream);
+
 /* ------------------------------------------------------------------------
  * Learned seed radius (not part of the paper; it only supplies the initial
  * value of a query leaf's bound, see knn_opts.seed_radius).

@@ -101,6 +101,14 @@ hipError_t launch_search_mfma_dp64(const SearchArgs &a, int K, int grid, hipStre
 // zero n 32-bit words with a kernel (api.hip)
 hipError_t zero_words(void *p, int64_t n, hipStream_t s);
 
+// k-furthest-neighbour kernels (search_far_d*.hip), stride 4 .. 64, lists of
+// 8, 16, 32 or 64
+hipError_t launch_search_far_dp4(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_far_dp8(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_far_dp16(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_far_dp32(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_far_dp64(const SearchArgs &a, int K, int grid, hipStream_t s);
+
 // compile-time list lengths; a request for a list of kk entries (k, or k+1
 // when the query's own point shares the list) uses the smallest K >= kk
 constexpr int kListSizes[] = {4, 5, 8, 10, 11, 16, 32, 50, 51, 64};

@@ -103,6 +103,8 @@ _SIGS = {
     "knn_mlp_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_P)]),
     "knn_seed_features": (ctypes.c_int, [_P, _P, _P, _P]),
     "knn_seed_radius": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_float, _P, _P]),
+    "knn_search_furthest": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts), _P,
+                                           _P, _P]),
     "knn_search_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts), _P,
                                           _P, _P]),
     "knn_debug_search_log": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts),
@@ -304,6 +306,20 @@ def knn_search(ref: Tree, query: Tree | None, k: int, bound="B", precision="fp32
     _check(load().knn_search(ref.handle, query.handle if query is not None else None, int(k),
                              ctypes.byref(o), ctypes.c_void_p(idx.data_ptr()),
                              ctypes.c_void_p(dist.data_ptr()), _stream(stream)))
+    return idx, dist, _stats_dict(st)
+
+
+def knn_search_furthest(ref: Tree, query: Tree | None, k: int, bound="B", exclude_self=False,
+                        stats=False, out=None, stream=None):
+    """The k FARTHEST reference points of every query point (query None: ref
+    on itself).  Returns (idx int64 [n_q, k], dist float32 [n_q, k]
+    descending, stats dict or None)."""
+    qt = query or ref
+    idx, dist = _outputs(out, qt.n, k)
+    o, st = _make_opts(bound, "fp32", exclude_self, None, None, stats)
+    _check(load().knn_search_furthest(ref.handle, query.handle if query is not None else None,
+                                      int(k), ctypes.byref(o), ctypes.c_void_p(idx.data_ptr()),
+                                      ctypes.c_void_p(dist.data_ptr()), _stream(stream)))
     return idx, dist, _stats_dict(st)
 
 
