@@ -287,3 +287,44 @@ class DualTreeKFN(DualTreeKNN):
             order = sorted(cr, key=lambda x: -self._dmax(c, x))
             for x in order:
                 self.traverse(c, x)
+
+
+class DualTreeRange(DualTreeKNN):
+    """Literal range search (Section "Range Search", Algorithms 5 and 6): the
+    BaseCase adds every reference whose distance lies in [lo, hi]; Score
+    keeps a node pair while some of its pairs may lie in the range.
+
+    Score reading.  As printed, Algorithm 6 keeps a pair only when
+    lo <= d_min(N_q, N_r) <= hi, which also discards a pair whose d_min is
+    below lo although its farther points lie inside the range (for instance
+    any pair of overlapping nodes when lo > 0).  The safe reading keeps the
+    pair unless every distance misses the range: prune iff d_min > hi or
+    d_max < lo.  ``printed=True`` uses the printed test, for the test that
+    shows the difference."""
+
+    def __init__(self, qpts, rpts, lo, hi, leaf_size=2, exclude_self=False, printed=False):
+        super().__init__(qpts, rpts, 1, leaf_size, "none", exclude_self)
+        self.lo, self.hi, self.printed = lo, hi, printed
+        self.found = [set() for _ in range(self.q.shape[0])]
+
+    def score(self, nq, nr):
+        self.score_calls += 1
+        dmin = self._dmin(nq, nr)
+        if self.printed:
+            return dmin if self.lo <= dmin <= self.hi else math.inf
+        dmax = DualTreeKFN._dmax(self, nq, nr)
+        return math.inf if (dmin > self.hi or dmax < self.lo) else dmin
+
+    def base_case(self, iq, ir):
+        if self.exclude_self and iq == ir:
+            return 0.0
+        self.base_cases += 1
+        diff = self.q[iq] - self.r[ir]
+        s = float(diff @ diff)
+        if self.lo * self.lo <= s <= self.hi * self.hi:
+            self.found[iq].add(ir)
+        return math.sqrt(s)
+
+    def run(self):
+        self.traverse(0, 0)
+        return [np.array(sorted(f), np.int64) for f in self.found]

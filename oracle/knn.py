@@ -41,6 +41,9 @@ def _load():
         lib.knn_oracle_threads.restype = ctypes.c_int
         lib.knn_oracle_furthest_rows.argtypes = [p, p, i64, p, i64, i32, i32, i32, p, p]
         lib.knn_oracle_furthest_rows.restype = ctypes.c_int
+        lib.knn_oracle_range_rows.argtypes = [p, p, i64, p, i64, i32, ctypes.c_double,
+                                              ctypes.c_double, i32, p, p, p, p]
+        lib.knn_oracle_range_rows.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -148,3 +151,51 @@ def furthest_numpy(q, r, k: int, exclude_self: bool = False):
         np.fill_diagonal(d2, -np.inf)
     order = np.argsort(-d2, axis=1, kind="stable")[:, :k]
     return order.astype(np.int64), np.take_along_axis(d2, order, axis=1)
+
+
+# --------------------------------------------------------------------------
+# Range search (Section "Range Search"): every reference at a distance in
+# [lo, hi], decided on FP64 squared distances (lo^2 <= s <= hi^2).
+# --------------------------------------------------------------------------
+def range_rows(q, rows, r, lo: float, hi: float, exclude_self: bool = False):
+    """Queries ``q[rows]``.  Returns (offsets int64 [len(rows)+1], idx int64,
+    d2 float64): the neighbours of row t are idx[offsets[t]:offsets[t+1]] in
+    increasing reference index."""
+    q, r = _f32(q), _f32(r)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    n = len(rows)
+    counts = np.empty(n, np.int64)
+    lib = _load()
+    rc = lib.knn_oracle_range_rows(q.ctypes.data, rows.ctypes.data, n, r.ctypes.data,
+                                   r.shape[0], q.shape[1], float(lo), float(hi),
+                                   int(bool(exclude_self)), counts.ctypes.data, None, None, None)
+    if rc != 0:
+        raise ValueError("oracle: invalid arguments (need 0 <= lo <= hi)")
+    offsets = np.zeros(n + 1, np.int64)
+    np.cumsum(counts, out=offsets[1:])
+    idx = np.empty(offsets[-1], np.int64)
+    d2 = np.empty(offsets[-1], np.float64)
+    lib.knn_oracle_range_rows(q.ctypes.data, rows.ctypes.data, n, r.ctypes.data, r.shape[0],
+                              q.shape[1], float(lo), float(hi), int(bool(exclude_self)),
+                              counts.ctypes.data, offsets.ctypes.data, idx.ctypes.data,
+                              d2.ctypes.data)
+    return offsets, idx, d2
+
+
+def range_search(q, r, lo: float, hi: float, exclude_self: bool = False):
+    return range_rows(q, np.arange(len(q)), r, lo, hi, exclude_self)
+
+
+def range_numpy(q, r, lo: float, hi: float, exclude_self: bool = False):
+    """The same definition in numpy (tiny inputs): a list of index arrays."""
+    q = np.asarray(q, np.float32).astype(np.float64)
+    r = np.asarray(r, np.float32).astype(np.float64)
+    out = []
+    for i in range(len(q)):
+        diff = r - q[i]
+        s = (diff * diff).sum(1)
+        keep = (s >= lo * lo) & (s <= hi * hi)
+        if exclude_self:
+            keep[i] = False
+        out.append(np.nonzero(keep)[0])
+    return out

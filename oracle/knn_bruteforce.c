@@ -207,3 +207,51 @@ int knn_oracle_furthest_rows(const float *q, const int64_t *qsel, int64_t nsel,
     }
     return 0;
 }
+
+/*
+ * Range search (Section "Range Search", problem statement): for each
+ * selected query every reference at a distance in [lo, hi], both ends
+ * included.  The decision is taken on squared distances in FP64:
+ * lo*lo <= s <= hi*hi with s the FP64 squared distance of the FP32 inputs.
+ * exclude_self skips reference qsel[t] for query row t.
+ *
+ * knn_oracle_range_rows fills counts_out[t] (the number of neighbours of
+ * row t); with idx_out != NULL it also writes them, in increasing reference
+ * index, at idx_out[offsets[t] ..] with squared distances in d2_out
+ * (offsets: exclusive prefix sums of the counts, supplied by the caller).
+ */
+int knn_oracle_range_rows(const float *q, const int64_t *qsel, int64_t nsel,
+                          const float *r, int64_t m, int32_t d, double lo, double hi,
+                          int32_t exclude_self, int64_t *counts_out,
+                          const int64_t *offsets, int64_t *idx_out, double *d2_out)
+{
+    if (!q || !qsel || !r || !counts_out || nsel < 0 || m <= 0 || d <= 0 || !(lo >= 0.0) ||
+        !(hi >= lo) || (idx_out && (!offsets || !d2_out)))
+        return -1;
+    const double lo2 = lo * lo, hi2 = hi * hi;
+    int64_t t;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (t = 0; t < nsel; ++t) {
+        int64_t i = qsel[t];
+        const float *qi = q + i * (int64_t)d;
+        int64_t c = 0;
+        for (int64_t j = 0; j < m; ++j) {
+            if (exclude_self && j == i) continue;
+            const float *rj = r + j * (int64_t)d;
+            double s = 0.0;
+            for (int u = 0; u < d; ++u) {
+                double diff = (double)qi[u] - (double)rj[u];
+                s += diff * diff;
+            }
+            if (s >= lo2 && s <= hi2) {
+                if (idx_out) {
+                    idx_out[offsets[t] + c] = j;
+                    d2_out[offsets[t] + c] = s;
+                }
+                ++c;
+            }
+        }
+        counts_out[t] = c;
+    }
+    return 0;
+}
