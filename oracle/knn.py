@@ -44,6 +44,8 @@ def _load():
         lib.knn_oracle_range_rows.argtypes = [p, p, i64, p, i64, i32, ctypes.c_double,
                                               ctypes.c_double, i32, p, p, p, p]
         lib.knn_oracle_range_rows.restype = ctypes.c_int
+        lib.knn_oracle_kde_rows.argtypes = [p, p, i64, p, i64, i32, ctypes.c_double, i32, p, p]
+        lib.knn_oracle_kde_rows.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -199,3 +201,36 @@ def range_numpy(q, r, lo: float, hi: float, exclude_self: bool = False):
             keep[i] = False
         out.append(np.nonzero(keep)[0])
     return out
+
+
+# --------------------------------------------------------------------------
+# Kernel density sums (Section "Kernel Density Estimation"): f(q) = sum over
+# references of exp(-||q - r||^2 / (2 h^2)), FP64.
+# --------------------------------------------------------------------------
+def kde_rows(q, rows, r, h: float, exclude_self: bool = False):
+    """Queries ``q[rows]``.  Returns (f, budget) float64: the exact sums and
+    sum K (1 + d^2 / 2h^2), the scale of FP32 evaluation error."""
+    q, r = _f32(q), _f32(r)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    f = np.empty(len(rows), np.float64)
+    b = np.empty(len(rows), np.float64)
+    rc = _load().knn_oracle_kde_rows(q.ctypes.data, rows.ctypes.data, len(rows), r.ctypes.data,
+                                     r.shape[0], q.shape[1], float(h), int(bool(exclude_self)),
+                                     f.ctypes.data, b.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle: invalid arguments (need h > 0)")
+    return f, b
+
+
+def kde(q, r, h: float, exclude_self: bool = False):
+    return kde_rows(q, np.arange(len(q)), r, h, exclude_self)
+
+
+def kde_numpy(q, r, h: float, exclude_self: bool = False):
+    q = np.asarray(q, np.float32).astype(np.float64)
+    r = np.asarray(r, np.float32).astype(np.float64)
+    diff = q[:, None, :] - r[None, :, :]
+    k = np.exp(-(diff * diff).sum(-1) / (2.0 * h * h))
+    if exclude_self:
+        np.fill_diagonal(k, 0.0)
+    return k.sum(1)

@@ -255,3 +255,42 @@ int knn_oracle_range_rows(const float *q, const int64_t *qsel, int64_t nsel,
     }
     return 0;
 }
+
+/*
+ * Kernel density sums (Section "Kernel Density Estimation"): for each
+ * selected query f = sum over references of K(||q - r||) with the Gaussian
+ * kernel K(d) = exp(-d^2 / (2 h^2)) (no normalising constant), in FP64.
+ * budget_out (optional) receives sum of K(d) (1 + d^2 / (2 h^2)), the scale
+ * of the FP32 rounding of a sum whose terms are evaluated from FP32 squared
+ * distances.  exclude_self skips reference qsel[t] for row t.
+ */
+int knn_oracle_kde_rows(const float *q, const int64_t *qsel, int64_t nsel, const float *r,
+                        int64_t m, int32_t d, double h, int32_t exclude_self, double *f_out,
+                        double *budget_out)
+{
+    if (!q || !qsel || !r || !f_out || nsel < 0 || m <= 0 || d <= 0 || !(h > 0.0))
+        return -1;
+    const double c = 1.0 / (2.0 * h * h);
+    int64_t t;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (t = 0; t < nsel; ++t) {
+        int64_t i = qsel[t];
+        const float *qi = q + i * (int64_t)d;
+        double f = 0.0, b = 0.0;
+        for (int64_t j = 0; j < m; ++j) {
+            if (exclude_self && j == i) continue;
+            const float *rj = r + j * (int64_t)d;
+            double s = 0.0;
+            for (int u = 0; u < d; ++u) {
+                double diff = (double)qi[u] - (double)rj[u];
+                s += diff * diff;
+            }
+            const double x = s * c, k = exp(-x);
+            f += k;
+            b += k * (1.0 + x);
+        }
+        f_out[t] = f;
+        if (budget_out) budget_out[t] = b;
+    }
+    return 0;
+}
