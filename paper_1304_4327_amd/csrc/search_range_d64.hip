@@ -1,0 +1,8 @@
+// Instantiation of the range-search kernels for stride 64.
+#include "search_range.hpp"
+
+namespace knnx {
+hipError_t launch_range_dp64(const RangeArgs &a, int lg, bool fill, int grid, hipStream_t s) {
+    return launch_range<64>(a, lg, fill, grid, s);
+}
+}  // namespace knnx
