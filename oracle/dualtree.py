@@ -386,3 +386,111 @@ class DualTreeKDE(DualTreeKNN):
     def run(self):
         self.traverse(0, 0)
         return self.f.copy()
+
+
+class DualTreeBoruvka(DualTreeKNN):
+    """Literal dual-tree Boruvka (Section "Boruvka's Algorithm", Algorithms 7
+    and 8 and the traversal-merge loop) on one kd-tree used as both trees.
+
+    Per round, for every component F_i: D(F_i), N(F_i), p_c(F_i).  BaseCase
+    (Algorithm 7) offers the pair (p_q, p_r) to F(p_q) when the two lie in
+    different components; Score (Algorithm 8) prunes a node pair whose points
+    all lie in one component, or whose d_min exceeds B(N_q).  After the
+    traversal each component's edge (p_c, N) is added and components joined
+    by an edge are merged, until one remains.
+
+    Readings.
+    * Ties: the BaseCase comparison "d < D(F(p_q))" keeps the first of equal
+      distances, which depends on visit order and, with equal-length edges,
+      can close a cycle; candidates are compared by the strict total order
+      (squared length, smaller index, larger index) instead, under which the
+      minimum spanning tree is unique and Boruvka's merges never form a
+      cycle.  The prune is strict (d_min > B), so a tie is never pruned.
+    * The bound is Section 5's B(N_q) with k = 1 and D_p[1] = D(F(p)) (the
+      safe reading, without the printed child term): B1 = max_p D(F(p)),
+      B2 = min_p D(F(p)) + 2 lambda(N_q), and the parent's.  B2 stays a
+      bound although D(F(p)) is realised elsewhere in the component: if the
+      node holds points of two components, each of them has an edge of
+      length at most 2 lambda (between those two points), so its shortest
+      edge is at most B2; if it holds one component c, B2 >= D(c) = B1.
+      ``bound`` is "B" (all terms), "B1" (max term and parent) or "none"
+      (prune only node pairs inside one component)."""
+
+    def __init__(self, pts, leaf_size=2, bound="B"):
+        super().__init__(pts, pts, 1, leaf_size, "none", False)
+        self.mode = bound
+        n = self.q.shape[0]
+        self.F = np.arange(n)
+        self.edges = []
+        self.rounds = 0
+
+    def _same_component(self, nq, nr):
+        a = self.F[self._points(self.tq, nq)]
+        b = self.F[self._points(self.tr, nr)]
+        return a.size == 0 or b.size == 0 or (np.all(a == a[0]) and np.all(b == a[0]))
+
+    def _B(self, node):
+        if self.mode == "none":
+            return math.inf
+        pts = self._points(self.tq, node)
+        if pts.size == 0:
+            return math.inf
+        dk = np.array([self.D[self.F[p]] for p in pts])
+        b = dk.max()
+        if self.mode == "B":
+            b = min(b, dk.min() + 2.0 * self.tq["lam"][node])
+        if node > 0:
+            b = min(b, self._B((node - 1) // 2))
+        return b
+
+    def score(self, nq, nr):
+        self.score_calls += 1
+        if self._same_component(nq, nr):
+            return math.inf
+        dmin = self._dmin(nq, nr)
+        return math.inf if dmin > self._B(nq) else dmin
+
+    def base_case(self, iq, ir):
+        if iq == ir:
+            return 0.0
+        self.base_cases += 1
+        diff = self.q[iq] - self.q[ir]
+        s = float(diff @ diff)
+        c = self.F[iq]
+        if self.F[ir] != c:
+            key = (s, min(iq, ir), max(iq, ir))
+            if self.best[c] is None or key < self.best[c]:
+                self.best[c] = key
+                self.D[c] = math.sqrt(s)
+        return math.sqrt(s)
+
+    def run(self):
+        n = self.q.shape[0]
+        while len(set(self.F.tolist())) > 1:
+            self.rounds += 1
+            self.D = np.full(n, math.inf)     # indexed by component label
+            self.best = [None] * n
+            self.traverse(0, 0)
+            # merge: every component's edge, once
+            chosen = {self.best[c] for c in set(self.F.tolist()) if self.best[c] is not None}
+            parent = list(range(n))
+
+            def root(a):
+                while parent[a] != a:
+                    parent[a] = parent[parent[a]]
+                    a = parent[a]
+                return a
+
+            for (s, a, b) in sorted(chosen):
+                ra, rb = root(self.F[a]), root(self.F[b])
+                if ra == rb:
+                    raise RuntimeError("a chosen edge closes a cycle")
+                parent[ra] = rb
+                self.edges.append((a, b, s))
+            self.F = np.array([root(self.F[i]) for i in range(n)])
+            if not chosen:
+                raise RuntimeError("no edge found while several components remain")
+        if not self.edges:
+            return np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0)
+        u, v, w = zip(*self.edges)
+        return np.array(u, np.int64), np.array(v, np.int64), np.array(w)

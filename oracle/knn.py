@@ -46,6 +46,8 @@ def _load():
         lib.knn_oracle_range_rows.restype = ctypes.c_int
         lib.knn_oracle_kde_rows.argtypes = [p, p, i64, p, i64, i32, ctypes.c_double, i32, p, p]
         lib.knn_oracle_kde_rows.restype = ctypes.c_int
+        lib.knn_oracle_emst.argtypes = [p, i64, i32, p, p, p]
+        lib.knn_oracle_emst.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -234,3 +236,58 @@ def kde_numpy(q, r, h: float, exclude_self: bool = False):
     if exclude_self:
         np.fill_diagonal(k, 0.0)
     return k.sum(1)
+
+
+# --------------------------------------------------------------------------
+# Euclidean minimum spanning tree (Section "Boruvka's Algorithm"): unique
+# under the edge order (squared length, smaller index, larger index).
+# --------------------------------------------------------------------------
+def emst(x):
+    """Prim's algorithm in FP64 (C).  Returns (u int64 [n-1], v int64, d2
+    float64) with u < v, in the order Prim adds the edges."""
+    x = _f32(x)
+    n = x.shape[0]
+    u = np.empty(max(n - 1, 0), np.int64)
+    v = np.empty(max(n - 1, 0), np.int64)
+    d2 = np.empty(max(n - 1, 0), np.float64)
+    rc = _load().knn_oracle_emst(x.ctypes.data, n, x.shape[1], u.ctypes.data, v.ctypes.data,
+                                 d2.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle: invalid arguments")
+    return u, v, d2
+
+
+def emst_kruskal(x):
+    """Kruskal's algorithm in numpy (tiny inputs): every edge sorted by
+    (squared length, smaller index, larger index), union-find."""
+    x = np.asarray(x, np.float32).astype(np.float64)
+    n = len(x)
+    iu, iv = np.triu_indices(n, 1)
+    diff = x[iu] - x[iv]
+    d2 = (diff * diff).sum(1)
+    order = np.lexsort((iv, iu, d2))
+    parent = list(range(n))
+
+    def root(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    out = []
+    for e in order:
+        a, b = root(iu[e]), root(iv[e])
+        if a != b:
+            parent[a] = b
+            out.append((iu[e], iv[e], d2[e]))
+    if not out:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0)
+    u, v, w = zip(*out)
+    return np.array(u, np.int64), np.array(v, np.int64), np.array(w)
+
+
+def edge_set(u, v):
+    """Canonical form of an edge list: sorted (min, max) pairs."""
+    a, b = np.minimum(u, v), np.maximum(u, v)
+    o = np.lexsort((b, a))
+    return np.stack([a[o], b[o]], 1)

@@ -294,3 +294,75 @@ int knn_oracle_kde_rows(const float *q, const int64_t *qsel, int64_t nsel, const
     }
     return 0;
 }
+
+/*
+ * Euclidean minimum spanning tree (Section "Boruvka's Algorithm": the tree
+ * the dual-tree Boruvka iteration ends with) by Prim's algorithm on the
+ * complete graph, FP64 squared distances of the FP32 points.  Edges are
+ * compared by the strict total order (squared length, smaller endpoint
+ * index, larger endpoint index), under which the tree is unique.
+ * Outputs n - 1 edges in the order Prim adds them: edge_u < edge_v
+ * (point indices) and the squared length in edge_d2.  Returns 0, or -1 on
+ * invalid arguments.
+ */
+static int edge_before(double da, int64_t ua, int64_t va, double db, int64_t ub, int64_t vb)
+{
+    if (da != db) return da < db;
+    if (ua != ub) return ua < ub;
+    return va < vb;
+}
+
+int knn_oracle_emst(const float *x, int64_t n, int32_t d, int64_t *edge_u, int64_t *edge_v,
+                    double *edge_d2)
+{
+    if (!x || n < 1 || d <= 0 || (n > 1 && (!edge_u || !edge_v || !edge_d2))) return -1;
+    char *in = (char *)calloc((size_t)n, 1);
+    double *key = (double *)malloc(sizeof(double) * (size_t)n);
+    int64_t *from = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!in || !key || !from) {
+        free(in); free(key); free(from);
+        return -1;
+    }
+    for (int64_t j = 0; j < n; ++j) { key[j] = INFINITY; from[j] = -1; }
+    int64_t cur = 0;
+    in[0] = 1;
+    for (int64_t step = 0; step + 1 < n; ++step) {
+        /* the new tree vertex updates every outside vertex's best edge */
+        const float *xc = x + cur * (int64_t)d;
+        int64_t j;
+#pragma omp parallel for schedule(static)
+        for (j = 0; j < n; ++j) {
+            if (in[j]) continue;
+            const float *xj = x + j * (int64_t)d;
+            double s = 0.0;
+            for (int u = 0; u < d; ++u) {
+                double diff = (double)xc[u] - (double)xj[u];
+                s += diff * diff;
+            }
+            int64_t a = cur < j ? cur : j, b = cur < j ? j : cur;
+            int64_t fa = from[j] < 0 ? 0 : (from[j] < j ? from[j] : j);
+            int64_t fb = from[j] < 0 ? 0 : (from[j] < j ? j : from[j]);
+            if (from[j] < 0 || edge_before(s, a, b, key[j], fa, fb)) {
+                key[j] = s;
+                from[j] = cur;
+            }
+        }
+        /* the outside vertex with the smallest best edge joins */
+        int64_t best = -1;
+        for (j = 0; j < n; ++j) {
+            if (in[j]) continue;
+            if (best < 0) { best = j; continue; }
+            int64_t a = from[j] < j ? from[j] : j, b = from[j] < j ? j : from[j];
+            int64_t ba = from[best] < best ? from[best] : best;
+            int64_t bb = from[best] < best ? best : from[best];
+            if (edge_before(key[j], a, b, key[best], ba, bb)) best = j;
+        }
+        in[best] = 1;
+        edge_u[step] = from[best] < best ? from[best] : best;
+        edge_v[step] = from[best] < best ? best : from[best];
+        edge_d2[step] = key[best];
+        cur = best;
+    }
+    free(in); free(key); free(from);
+    return 0;
+}
