@@ -262,6 +262,77 @@ knn_status knn_search_furthest(const knn_tree *ref, const knn_tree *query, int32
                                const knn_opts *opts, int64_t *idx_out, float *dist_out,
                                void *stream);
 
+/* Range search (Section "Range Search", Algorithms 5 and 6): for every query
+ * point, every reference point at a distance in [lo, hi] (both ends
+ * included), decided exactly: lo*lo <= s <= hi*hi in FP64, with s the FP64
+ * squared distance of the FP32 inputs.  Score prunes a node pair only when
+ * every distance misses the range (d_min > hi or d_max < lo, with a 2^-16
+ * slack); the printed test on d_min alone is not used because it drops
+ * overlapping nodes whose farther points are in range.
+ * Two calls with the same trees, range and opts:
+ *   knn_range_count writes offsets_out (device, n_q + 1 int64): exclusive
+ *     prefix sums of the per-query neighbour counts in original query order
+ *     (offsets_out[0] = 0), and *total_out (host) = offsets_out[n_q];
+ *   knn_range_fill writes the neighbours of query i at
+ *     idx_out[offsets[i] .. offsets[i+1]-1] (device int64, original
+ *     reference rows) and their distances at the same places of dist_out
+ *     (device FP32 of the FP64 distance); the caller allocates both with
+ *     total entries.  Within a query the order is the traversal's
+ *     (deterministic; the paper's lists are unordered).
+ * opts: bound (KNN_BOUND_NONE: no pruning, anything else: the range test),
+ * exclude_self; precision FP32 and no seed or leaf output (else
+ * KNN_E_UNSUPPORTED); stats (per call; inserts = neighbours found).
+ * Domain: 0 <= lo <= hi < inf, n_q <= 2^24.  Errors: KNN_E_INVALID_ARG,
+ * KNN_E_UNSUPPORTED, KNN_E_OOM, KNN_E_DEVICE. */
+knn_status knn_range_count(const knn_tree *ref, const knn_tree *query, double lo, double hi,
+                           const knn_opts *opts, int64_t *offsets_out, int64_t *total_out,
+                           void *stream);
+knn_status knn_range_fill(const knn_tree *ref, const knn_tree *query, double lo, double hi,
+                          const knn_opts *opts, const int64_t *offsets, int64_t *idx_out,
+                          float *dist_out, void *stream);
+
+/* Kernel density sums (Section "Kernel Density Estimation", Algorithms 9 and
+ * 10): f_out[i] (device, n_q FP64, original query order) estimates
+ * f(q_i) = sum over reference points r of K(||q_i - r||) with the Gaussian
+ * kernel K(d) = exp(-d^2 / (2 h^2)) (no normalising constant), such that
+ * |f_out[i] - f(q_i)| <= eps for every query, plus FP32 evaluation error of
+ * the kernel values (relative about 1e-6 per term).  For a query node N_q
+ * (a group of query leaves) and a reference node N_r whose kernel values
+ * vary by less than eps / |S_r| (K(d_min) - K(d_max) between their boxes),
+ * each query point q of N_q adds |N_r| K(||q - C||), C the reference box
+ * centre, instead of N_r's points (the printed Algorithm 9 compares the
+ * other way round; the text and the error bound need this way).  opts: bound
+ * KNN_BOUND_NONE (or eps = 0) sums every pair exactly, anything else
+ * approximates as described; exclude_self (leave-one-out: skip each point's
+ * own term); stats (inserts = approximated (query point, node) pairs);
+ * precision FP32, no seed or leaf output (else KNN_E_UNSUPPORTED).
+ * Domain: h > 0, eps >= 0, both finite.  Errors: KNN_E_INVALID_ARG,
+ * KNN_E_UNSUPPORTED, KNN_E_OOM, KNN_E_DEVICE. */
+knn_status knn_kde(const knn_tree *ref, const knn_tree *query, double h, double eps,
+                   const knn_opts *opts, double *f_out, void *stream);
+
+/* Euclidean minimum spanning tree of a tree's points by dual-tree Boruvka
+ * (Section "Boruvka's Algorithm", Algorithms 7 and 8 and the
+ * traversal-merge loop), with the tree as both query and reference tree.
+ * Each round finds, for every component, its shortest edge to another
+ * component (the k = 1 traversal with the bound B(N_q) and a Score that
+ * prunes node pairs inside one component), then merges.  Edges are
+ * compared by the strict order (FP64 squared length of the FP32 points,
+ * smaller index, larger index), so the result is the unique minimum
+ * spanning tree under that order, edge for edge.
+ * Outputs (device, caller-owned, n - 1 entries each): edge_u[i] < edge_v[i]
+ * original point rows, edge_w[i] = FP32 of the FP64 length; the order is
+ * deterministic (by the tree position of the component that chose the
+ * edge), not sorted.  *rounds_out (host, optional): Boruvka rounds.
+ * opts: bound (KNN_BOUND_B, KNN_BOUND_B1, or KNN_BOUND_NONE: prune only
+ * pairs inside one component), stats (summed over rounds; ms_search is the
+ * whole computation); precision FP32, no seed or leaf output, no
+ * exclude_self (else KNN_E_UNSUPPORTED / KNN_E_INVALID_ARG).
+ * Domain: n <= 2^24.  Errors: KNN_E_INVALID_ARG, KNN_E_UNSUPPORTED,
+ * KNN_E_OOM, KNN_E_DEVICE. */
+knn_status knn_emst(const knn_tree *tree, const knn_opts *opts, int64_t *edge_u, int64_t *edge_v,
+                    float *edge_w, int32_t *rounds_out, void *stream);
+
 /* ------------------------------------------------------------------------
  * Learned seed radius (not part of the paper; it only supplies the initial
  * value of a query leaf's bound, see knn_opts.seed_radius).

@@ -15,72 +15,6 @@ hipError_t launch_range_dp64(const RangeArgs &a, int lg, bool fill, int grid, hi
 
 namespace {
 
-constexpr int kScanThreads = 1024;
-constexpr int kScanItems = 4;                          // per thread
-constexpr int kScanBlock = kScanThreads * kScanItems;  // per workgroup
-constexpr int64_t kMaxScan = int64_t(kScanBlock) * kScanBlock;
-
-// inclusive scan of one workgroup's values (one per thread) in LDS
-__device__ int64_t block_inclusive(int64_t v, int64_t *sh) {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        const int64_t u = t >= off ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += u;
-        __syncthreads();
-    }
-    return sh[t];
-}
-
-// out[i + 1] = sum of in[block start .. i] (within the block); tops[b] = the
-// block's total
-__global__ __launch_bounds__(kScanThreads) void k_scan_local(const int64_t *__restrict__ in,
-                                                             int64_t n, int64_t *__restrict__ out,
-                                                             int64_t *__restrict__ tops) {
-    __shared__ int64_t sh[kScanThreads];
-    const int64_t b0 = int64_t(blockIdx.x) * kScanBlock + int64_t(threadIdx.x) * kScanItems;
-    int64_t v[kScanItems], s = 0;
-#pragma unroll
-    for (int e = 0; e < kScanItems; ++e) {
-        v[e] = b0 + e < n ? in[b0 + e] : 0;
-        s += v[e];
-    }
-    int64_t run = block_inclusive(s, sh) - s;
-#pragma unroll
-    for (int e = 0; e < kScanItems; ++e) {
-        run += v[e];
-        if (b0 + e < n) out[b0 + e + 1] = run;
-    }
-    if (threadIdx.x == kScanThreads - 1) tops[blockIdx.x] = sh[kScanThreads - 1];
-}
-
-// exclusive scan of the block totals (one workgroup: at most kScanBlock)
-__global__ __launch_bounds__(kScanThreads) void k_scan_tops(int64_t *__restrict__ tops, int nb,
-                                                            int64_t *__restrict__ out) {
-    __shared__ int64_t sh[kScanThreads];
-    const int b0 = threadIdx.x * kScanItems;
-    int64_t v[kScanItems], s = 0;
-#pragma unroll
-    for (int e = 0; e < kScanItems; ++e) {
-        v[e] = b0 + e < nb ? tops[b0 + e] : 0;
-        s += v[e];
-    }
-    int64_t run = block_inclusive(s, sh) - s;
-#pragma unroll
-    for (int e = 0; e < kScanItems; ++e) {
-        if (b0 + e < nb) tops[b0 + e] = run;
-        run += v[e];
-    }
-    if (threadIdx.x == 0) out[0] = 0;
-}
-
-__global__ void k_scan_add(int64_t *__restrict__ out, int64_t n, const int64_t *__restrict__ tops) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) out[i + 1] += tops[i / kScanBlock];
-}
-
 hipError_t launch_dp(const RangeArgs &a, int dp, int lg, bool fill, int grid, hipStream_t s) {
     switch (dp) {
         case 4: return launch_range_dp4(a, lg, fill, grid, s);
@@ -103,7 +37,7 @@ knn_status prepare(const char *who, const knn_tree *ref, const knn_tree *query, 
     if (qt->d != ref->d) return fail(KNN_E_INVALID_ARG, w + ": d differs");
     if (!(lo >= 0.0) || !(hi >= lo) || !std::isfinite(hi))
         return fail(KNN_E_INVALID_ARG, w + ": need 0 <= lo <= hi < inf");
-    if (qt->n > kMaxScan) return fail(KNN_E_INVALID_ARG, w + ": need n_q <= 2^24");
+    if (qt->n > kScanMax) return fail(KNN_E_INVALID_ARG, w + ": need n_q <= 2^24");
     if (opts.exclude_self && qt != ref)
         return fail(KNN_E_INVALID_ARG, w + ": exclude_self needs the query tree to be the reference tree");
     if (opts.bound < 0 || opts.bound > 2 || opts.reserved != 0)
@@ -202,7 +136,6 @@ extern "C" knn_status knn_range_count(const knn_tree *ref, const knn_tree *query
         return fail(KNN_E_INVALID_ARG, "knn_range_count: an output pointer is NULL");
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = (query ? query : ref)->n;
-    const int nb = int((n + kScanBlock - 1) / kScanBlock);
     int64_t *counts = nullptr, *tops = nullptr;
     struct Guard {
         hipStream_t s;
@@ -214,14 +147,11 @@ extern "C" knn_status knn_range_count(const knn_tree *ref, const knn_tree *query
     } guard{s, nullptr, nullptr};
     KNN_HIP(alloc_async(&counts, size_t(n), s));
     guard.c = counts;
-    KNN_HIP(alloc_async(&tops, size_t(nb), s));
+    KNN_HIP(alloc_async(&tops, size_t(scan_scratch(n)), s));
     guard.t = tops;
     a.counts = counts;
     KNN_TRY(run_pass(a, ref, lg, false, grid, o, s));
-    k_scan_local<<<nb, kScanThreads, 0, s>>>(counts, n, offsets_out, tops);
-    k_scan_tops<<<1, kScanThreads, 0, s>>>(tops, nb, offsets_out);
-    k_scan_add<<<int((n + 255) / 256), 256, 0, s>>>(offsets_out, n, tops);
-    KNN_HIP(hipGetLastError());
+    KNN_HIP(exclusive_scan(counts, n, offsets_out, tops, s));
     KNN_HIP(hipMemcpyAsync(total_out, offsets_out + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     KNN_HIP(hipStreamSynchronize(s));
     return KNN_OK;

@@ -101,6 +101,13 @@ hipError_t launch_search_mfma_dp64(const SearchArgs &a, int K, int grid, hipStre
 // zero n 32-bit words with a kernel (api.hip)
 hipError_t zero_words(void *p, int64_t n, hipStream_t s);
 
+// exclusive prefix sums (scan.hip): out[0] = 0, out[i + 1] = in[0] + ... +
+// in[i] for 1 <= n <= kScanMax; tops is scratch of scan_scratch(n) values
+constexpr int64_t kScanMax = int64_t(1) << 24;
+int64_t scan_scratch(int64_t n);
+hipError_t exclusive_scan(const int64_t *in, int64_t n, int64_t *out, int64_t *tops,
+                          hipStream_t s);
+
 // k-furthest-neighbour kernels (search_far_d*.hip), stride 4 .. 64, lists of
 // 8, 16, 32 or 64
 hipError_t launch_search_far_dp4(const SearchArgs &a, int K, int grid, hipStream_t s);

@@ -73,6 +73,60 @@ __device__ __forceinline__ void tree_walk(int first_leaf, Score &&score, Leaf &&
     }
 }
 
+// The same walk with every node scored exactly once (when its parent is
+// expanded): the decision for the second child is remembered per depth
+// instead of scored again on the way back.  For rules whose Score has an
+// effect (kernel density's approximation adds a contribution).
+template <class Score, class Leaf, class Order>
+__device__ __forceinline__ void tree_walk_once(int first_leaf, Score &&score, Leaf &&leaf,
+                                               Order &&right_first) {
+    float m0, m1;
+    if (!score(0, m0)) return;
+    int node = 0, depth = 0;
+    uint64_t firstbits = 0, secondbits = 0;
+    bool down = true;
+    for (;;) {
+        bool at_leaf = false;
+        for (;;) {
+            if (down) {
+                if (node >= first_leaf) {
+                    at_leaf = true;
+                    break;
+                }
+                const int c0 = 2 * node + 1, c1 = c0 + 1;
+                const bool k0 = score(c0, m0);
+                const bool k1 = score(c1, m1);
+                if (!k0 && !k1) {
+                    down = false;
+                    continue;
+                }
+                const bool right = k1 && (!k0 || right_first(m0, m1));
+                const bool second = right ? k0 : k1;
+                const uint64_t bit = uint64_t(1) << depth;
+                firstbits = right ? (firstbits | bit) : (firstbits & ~bit);
+                secondbits = second ? (secondbits | bit) : (secondbits & ~bit);
+                node = uniform_i(right ? c1 : c0);
+                ++depth;
+            } else {
+                if (node == 0) break;
+                --depth;
+                const bool is_right = (node & 1) == 0;
+                const bool first_right = (firstbits >> depth) & 1;
+                if (is_right == first_right && ((secondbits >> depth) & 1)) {
+                    node = uniform_i(is_right ? node - 1 : node + 1);
+                    ++depth;
+                    down = true;
+                    continue;
+                }
+                node = uniform_i((node - 1) >> 1);
+            }
+        }
+        if (!at_leaf) break;
+        leaf(node);
+        down = false;
+    }
+}
+
 // squared distance from a point to a box: nearest (gap) and farthest point
 template <int DP>
 __device__ __forceinline__ void box_dist2(const float (&q)[DP], const float *b, float &dmin2,

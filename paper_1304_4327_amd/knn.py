@@ -105,6 +105,15 @@ _SIGS = {
     "knn_seed_radius": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_float, _P, _P]),
     "knn_search_furthest": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts), _P,
                                            _P, _P]),
+    "knn_range_count": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double,
+                                       ctypes.POINTER(knn_opts), _P, ctypes.POINTER(ctypes.c_int64),
+                                       _P]),
+    "knn_range_fill": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double,
+                                      ctypes.POINTER(knn_opts), _P, _P, _P, _P]),
+    "knn_kde": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.POINTER(knn_opts),
+                               _P, _P]),
+    "knn_emst": (ctypes.c_int, [_P, ctypes.POINTER(knn_opts), _P, _P, _P,
+                                ctypes.POINTER(ctypes.c_int32), _P]),
     "knn_search_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts), _P,
                                           _P, _P]),
     "knn_debug_search_log": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts),
@@ -321,6 +330,64 @@ def knn_search_furthest(ref: Tree, query: Tree | None, k: int, bound="B", exclud
                                       int(k), ctypes.byref(o), ctypes.c_void_p(idx.data_ptr()),
                                       ctypes.c_void_p(dist.data_ptr()), _stream(stream)))
     return idx, dist, _stats_dict(st)
+
+
+def knn_range_search(ref: Tree, query: Tree | None, lo: float, hi: float, bound="B",
+                     exclude_self=False, stats=False, stream=None):
+    """Every reference point at a distance in [lo, hi] of each query point.
+    Returns (offsets int64 [n_q + 1], idx int64 [total], dist float32
+    [total], (count stats, fill stats) or None): the neighbours of query i
+    are idx[offsets[i]:offsets[i+1]]."""
+    torch = _torch()
+    qt = query or ref
+    qh = query.handle if query is not None else None
+    offsets = torch.empty(qt.n + 1, dtype=torch.int64, device="cuda")
+    total = ctypes.c_int64()
+    o1, st1 = _make_opts(bound, "fp32", exclude_self, None, None, stats)
+    _check(load().knn_range_count(ref.handle, qh, float(lo), float(hi), ctypes.byref(o1),
+                                  ctypes.c_void_p(offsets.data_ptr()), ctypes.byref(total),
+                                  _stream(stream)))
+    idx = torch.empty(max(total.value, 1), dtype=torch.int64, device="cuda")
+    dist = torch.empty(max(total.value, 1), dtype=torch.float32, device="cuda")
+    o2, st2 = _make_opts(bound, "fp32", exclude_self, None, None, stats)
+    _check(load().knn_range_fill(ref.handle, qh, float(lo), float(hi), ctypes.byref(o2),
+                                 ctypes.c_void_p(offsets.data_ptr()),
+                                 ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(dist.data_ptr()),
+                                 _stream(stream)))
+    st = (_stats_dict(st1), _stats_dict(st2)) if stats else None
+    return offsets, idx[:total.value], dist[:total.value], st
+
+
+def knn_kde(ref: Tree, query: Tree | None, h: float, eps: float, bound="B", exclude_self=False,
+            stats=False, stream=None):
+    """Gaussian kernel sums f(q) = sum_r exp(-|q - r|^2 / 2h^2) within eps per
+    query.  Returns (f float64 [n_q], stats dict or None)."""
+    torch = _torch()
+    qt = query or ref
+    f = torch.empty(qt.n, dtype=torch.float64, device="cuda")
+    o, st = _make_opts(bound, "fp32", exclude_self, None, None, stats)
+    _check(load().knn_kde(ref.handle, query.handle if query is not None else None, float(h),
+                          float(eps), ctypes.byref(o), ctypes.c_void_p(f.data_ptr()),
+                          _stream(stream)))
+    return f, _stats_dict(st)
+
+
+def knn_emst(tree: Tree, bound="B", stats=False, stream=None):
+    """Euclidean minimum spanning tree of the tree's points (dual-tree
+    Boruvka).  Returns (u int64 [n-1], v int64, w float32, rounds, stats
+    dict or None) with u < v original rows."""
+    torch = _torch()
+    m = max(tree.n - 1, 1)
+    u = torch.empty(m, dtype=torch.int64, device="cuda")
+    v = torch.empty(m, dtype=torch.int64, device="cuda")
+    w = torch.empty(m, dtype=torch.float32, device="cuda")
+    rounds = ctypes.c_int32()
+    o, st = _make_opts(bound, "fp32", False, None, None, stats)
+    _check(load().knn_emst(tree.handle, ctypes.byref(o), ctypes.c_void_p(u.data_ptr()),
+                           ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                           ctypes.byref(rounds), _stream(stream)))
+    k = tree.n - 1
+    return u[:k], v[:k], w[:k], rounds.value, _stats_dict(st)
 
 
 def knn_search_noalloc(ref: Tree, query: Tree | None, k: int, out, bound="B", precision="fp32",
