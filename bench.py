@@ -78,6 +78,10 @@ def parse():
     ap.add_argument("--no-combined", action="store_true",
                     help="skip the learned+BF16 vs plain FP32 comparison on the d = 64 workload")
     ap.add_argument("--combined-train-seeds", type=int, default=4)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the k-furthest, range, KDE and EMST measurements")
+    ap.add_argument("--only-extras", action="store_true",
+                    help="run only the k-furthest, range, KDE and EMST measurements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (reference "
                          "kernel for scaling the HBM byte counters) and exit")
@@ -212,6 +216,135 @@ def combined(args):
     return line
 
 
+def extras(args):
+    """The other instances of the meta-algorithm, each timed on the d = 3
+    Gaussian-mixture workload (1M references, 1M queries, leaf 32) with
+    prebuilt trees, its dominant kernel's roofline figure, and the oracle
+    timed on a sample that also checks the answer."""
+    import numpy as np
+    import torch
+
+    from paper_1304_4327_amd import datagen, knn
+    ref, q, k, leaf = datagen.make("gmm1m_d3_k10")
+    d = ref.shape[1]
+    R, Q = torch.from_numpy(ref).cuda(), torch.from_numpy(q).cuda()
+    rt, qt = knn.knn_build_tree_pair(R, Q, leaf)
+    peak = PEAKS["fp32_vector_tflops"]
+    out = {"workload": "gmm1m_d3_k10", "n_ref": len(ref), "n_query": len(q), "d": d,
+           "leaf_size": leaf, "timed": "the operation on prebuilt trees (device events)"}
+
+    def roof(pairs, flop, ms):
+        ach = pairs * flop / (ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak, "flop_per_pair": flop, "pairs_per_launch": pairs}
+
+    rng = np.random.default_rng(77)
+    rows = np.sort(rng.choice(len(q), 1024, replace=False))
+
+    # k-furthest neighbours, k = 10
+    ms, outs = _timed(lambda: knn.knn_search_furthest(rt, qt, k, stats=True), 3, 1)
+    st = outs[-1][2]
+    far = {"k": k, "ms": st["ms_search"], "queries_per_s": len(q) / st["ms_search"] * 1e3,
+           "pairs_per_query": st["pairs"] / len(q),
+           "roofline": roof(st["pairs"], 3 * d - 1, st["ms_search"])}
+    gi, gd = outs[-1][0].cpu().numpy(), outs[-1][1].cpu().numpy()
+    print(f"extras: furthest {st['ms_search']:.2f} ms", file=sys.stderr, flush=True)
+    # range search, [0, 0.2]
+    lo, hi = 0.0, 0.2
+    ms, outs = _timed(lambda: knn.knn_range_search(rt, qt, lo, hi, stats=True), 3, 1)
+    sc, sf = outs[-1][3]
+    off = outs[-1][0].cpu().numpy()
+    rng_ = {"lo": lo, "hi": hi, "ms_count": sc["ms_search"], "ms_fill": sf["ms_search"],
+            "neighbours_per_query": float(off[-1]) / len(q),
+            "queries_per_s": len(q) / (sc["ms_search"] + sf["ms_search"]) * 1e3,
+            "pairs_per_query": sc["pairs"] / len(q),
+            "roofline": roof(sc["pairs"], 3 * d - 1, sc["ms_search"])}
+    rng_ans = (off, outs[-1][1].cpu().numpy())
+    print(f"extras: range {sc['ms_search']:.2f} + {sf['ms_search']:.2f} ms", file=sys.stderr,
+          flush=True)
+    # kernel density sums, h = 1, eps = 1
+    h, eps = 1.0, 1.0
+    ms, outs = _timed(lambda: knn.knn_kde(rt, qt, h, eps, stats=True), 3, 1)
+    st = outs[-1][1]
+    kde = {"h": h, "eps": eps, "ms": st["ms_search"],
+           "queries_per_s": len(q) / st["ms_search"] * 1e3,
+           "pairs_per_query": st["pairs"] / len(q),
+           "approximated_nodes_per_query": st["inserts"] / len(q),
+           # distance (3d - 1), scaling and exponential counted one each
+           "roofline": roof(st["pairs"], 3 * d + 1, st["ms_search"])}
+    f = outs[-1][0].cpu().numpy()
+    print(f"extras: kde {st['ms_search']:.2f} ms", file=sys.stderr, flush=True)
+    # minimum spanning tree of the reference set
+    ms, outs = _timed(lambda: knn.knn_emst(rt, stats=True), 2, 1)
+    u, v, w, rounds, st = outs[-1]
+    emst = {"n": len(ref), "ms": st["ms_search"], "rounds": rounds,
+            "points_per_s": len(ref) / st["ms_search"] * 1e3,
+            "pairs_per_point": st["pairs"] / len(ref),
+            "total_length": float(w.double().sum().item()),
+            "roofline": roof(st["pairs"], 3 * d - 1, st["ms_search"])}
+    print(f"extras: emst {st['ms_search']:.2f} ms, {rounds} rounds", file=sys.stderr, flush=True)
+    qt.close()
+    rt.close()
+    if not args.no_cpu_baseline:
+        base = extras_cpu_baseline(ref, q, k, rows, (gi, gd), rng_ans, (lo, hi), f, (h, eps),
+                                   (u.cpu().numpy(), v.cpu().numpy(), w.cpu().numpy()))
+        far["cpu_baseline"], rng_["cpu_baseline"], kde["cpu_baseline"], emst["cpu_baseline"] = base
+    out.update(k_furthest=far, range_search=rng_, kde=kde, emst=emst)
+    return out
+
+
+def extras_cpu_baseline(ref, q, k, rows, far_ans, rng_ans, rng_lohi, kde_f, kde_he, emst_uvw):
+    """The oracle for each extra timed on a seeded sample, which also checks
+    the GPU answer on that sample (range: identical sets; furthest: the
+    acceptance predicate; KDE: within eps plus the FP32 budget; EMST: the
+    total length of the 1M tree against no oracle -- Prim's O(n^2) is timed
+    on a 20k-point prefix and its tree checked against the GPU's on that
+    prefix)."""
+    import numpy as np
+    import torch
+
+    from oracle import knn as ok
+    from oracle import parity
+    from paper_1304_4327_amd import knn
+    cores = ok.threads()
+    res = []
+    t0 = time.perf_counter()
+    oi, od = ok.furthest_rows(q, rows, ref, k)
+    el = time.perf_counter() - t0
+    fails, _ = parity.check_furthest(q, ref, k, far_ans[0], far_ans[1], oi, od, rows=rows)
+    res.append({"value": len(rows) / el, "unit": "queries/s", "cores": cores, "kind": "oracle",
+                "sample": f"{len(rows)} seeded queries, {el:.2f} s",
+                "parity_ok": not any(fails.values())})
+    lo, hi = rng_lohi
+    t0 = time.perf_counter()
+    oo, oidx, _ = ok.range_rows(q, rows, ref, lo, hi)
+    el = time.perf_counter() - t0
+    off, idx = rng_ans
+    same = all(np.array_equal(np.sort(idx[off[r]:off[r + 1]]), oidx[oo[t]:oo[t + 1]])
+               for t, r in enumerate(rows))
+    res.append({"value": len(rows) / el, "unit": "queries/s", "cores": cores, "kind": "oracle",
+                "sample": f"{len(rows)} seeded queries, {el:.2f} s", "parity_ok": bool(same)})
+    h, eps = kde_he
+    t0 = time.perf_counter()
+    fe, budget = ok.kde_rows(q, rows, ref, h)
+    el = time.perf_counter() - t0
+    good = bool(np.all(np.abs(kde_f[rows] - fe) <= eps * (1 + 1e-5) + 2e-5 * budget))
+    res.append({"value": len(rows) / el, "unit": "queries/s", "cores": cores, "kind": "oracle",
+                "sample": f"{len(rows)} seeded queries, {el:.2f} s", "parity_ok": good})
+    sub = ref[:20000]
+    t0 = time.perf_counter()
+    pu, pv, _ = ok.emst(sub)
+    el = time.perf_counter() - t0
+    tr = knn.knn_build_tree(torch.from_numpy(sub).cuda(), 32)
+    gu, gv, _, _, _ = knn.knn_emst(tr)
+    same = np.array_equal(ok.edge_set(pu, pv), ok.edge_set(gu.cpu().numpy(), gv.cpu().numpy()))
+    tr.close()
+    res.append({"value": len(sub) / el, "unit": "points/s (Prim, O(n^2))", "cores": cores,
+                "kind": "oracle", "sample": f"the first 20000 reference points, {el:.2f} s",
+                "parity_ok": bool(same)})
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -220,6 +353,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.only_extras:
+        print(json.dumps({"extras": extras(args)}), flush=True)
         return
     import numpy as np
     import torch
@@ -362,6 +498,9 @@ def main():
     if not args.no_combined and args.workload != COMBINED_WORKLOAD:
         torch.cuda.empty_cache()
         line["compare_learned_bf16"] = combined(args)
+    if not args.no_extras:
+        torch.cuda.empty_cache()
+        line["extras"] = extras(args)
     print(json.dumps(line), flush=True)
 
 
