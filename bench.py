@@ -152,6 +152,37 @@ def _timed(run, steps, warmup):
     return (time.perf_counter() - t0) / steps * 1e3, sts
 
 
+def seed_ceiling(R, Q, k, leaf, precision, reps=3):
+    """What any learned seed could gain at best: the seeded search with the
+    ideal seed -- each query leaf's true largest k-th distance, reported by
+    a plain run (leaf_kth_out), nudged up so that no leaf falls back --
+    against the plain search, both on the same prebuilt trees."""
+    import numpy as np
+    import torch
+
+    from paper_1304_4327_amd import knn
+    rt, qt = knn.knn_build_tree_pair(R, Q, leaf)
+    nl = qt.info()["n_leaves"]
+    kth = torch.empty(nl, dtype=torch.float32, device="cuda")
+    knn.knn_search(rt, qt, k, precision=precision, leaf_kth_out=kth)
+    ideal = (kth.double() * (1 + 1e-5)).float().contiguous()
+
+    def run(seed):
+        return knn.knn_search(rt, qt, k, precision=precision, seed_radius=seed, stats=True)[2]
+
+    out = {}
+    for name, seed in (("plain", None), ("ideal_seed", ideal)):
+        run(seed)
+        sts = [run(seed) for _ in range(reps)]
+        out[name] = {"ms_search": float(np.mean([s["ms_search"] for s in sts])),
+                     "pairs_per_query": sts[0]["pairs"] / Q.shape[0],
+                     "fallback_leaves": sts[0]["fallback_leaves"]}
+    out["speedup_of_ideal_seed"] = out["plain"]["ms_search"] / out["ideal_seed"]["ms_search"]
+    qt.close()
+    rt.close()
+    return out
+
+
 def combined(args):
     """Learned seed + BF16 tiles against the plain FP32 traversal on the d = 64
     workload (plus plain BF16, and the B1 bound), every variant checked."""
@@ -200,6 +231,9 @@ def combined(args):
             res[key]["query_leaves"] = sts[0]["n_query_leaves"]
         answers[key] = (outs[-1][0].cpu().numpy(), outs[-1][1].cpu().numpy())
         print(f"combined: {key} {ms:.2f} ms/step", file=sys.stderr, flush=True)
+    ceiling = seed_ceiling(R, Q, k, leaf, "bf16")
+    print(f"combined: ideal seed {ceiling['speedup_of_ideal_seed']:.3f}x", file=sys.stderr,
+          flush=True)
     line = {"workload": name, "n_ref": len(ref), "n_query": nq, "d": ref.shape[1], "k": k,
             "baseline": "plain FP32 dual-tree traversal, bound B",
             "speedup_learned_bf16_vs_plain_fp32":
@@ -210,7 +244,8 @@ def combined(args):
                                               res["plain_bf16_B1"]["pairs_per_query"]],
             "variants": res,
             "seed_training": {"train_seeds": seeds, "eval_seed": base, "train_s": train_s,
-                              "log_margin": model.log_margin}}
+                              "log_margin": model.log_margin},
+            "seed_ceiling_bf16": ceiling}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ref, q, k, False, 5.0, answers)
     return line
@@ -490,6 +525,8 @@ def main():
                                fallback_pairs_per_query=float(np.mean([s["fallback_pairs"] for s in stats])) / nq,
                                ms_seeded_pass=float(np.mean([s["ms_main_kernel"] for s in stats])),
                                ms_search_total=float(np.mean([s["ms_search"] for s in stats])))
+    if not self_mode and not args.learned:
+        line["seed_ceiling"] = seed_ceiling(R, Q, k, leaf, args.precision)
     print(f"headline done: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ref, q, k, self_mode, args.cpu_seconds,
