@@ -527,6 +527,22 @@ def main():
                                ms_search_total=float(np.mean([s["ms_search"] for s in stats])))
     if not self_mode and not args.learned:
         line["seed_ceiling"] = seed_ceiling(R, Q, k, leaf, args.precision)
+    if d == 3 and args.precision == "fp32" and not args.learned and args.bound == "B":
+        # the BaseCase tiles alone: the search's recorded leaf list replayed
+        # without the walk (same tiles, same order, same answer)
+        rt, qt = (knn.knn_build_tree(R, leaf), None) if self_mode else \
+            knn.knn_build_tree_pair(R, Q, leaf)
+        reps = [knn.knn_debug_tile_replay(rt, qt, k, exclude_self=self_mode) for _ in range(3)]
+        tile_ms = float(np.mean([r[3] for r in reps]))
+        tile_pairs = reps[-1][4]
+        tach = tile_pairs * flop_per_pair / (tile_ms * 1e-3) / 1e12
+        line["roofline"].update(tile_ms=tile_ms, tile_achieved=tach, tile_frac=tach / peak,
+                                tile_note="the search's BaseCase tiles (distances, filter, "
+                                          "k-list inserts, bound refresh) replayed without "
+                                          "the walk and Score")
+        if qt is not None:
+            qt.close()
+        rt.close()
     print(f"headline done: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ref, q, k, self_mode, args.cpu_seconds,

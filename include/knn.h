@@ -406,6 +406,20 @@ knn_status knn_debug_bf16_tiles(const float *q, const float *r, const float *cen
                                 int64_t n_tiles, int32_t d, float *acc_out, float *qnorm_out,
                                 float *margin_out, void *stream);
 
+/* The BaseCase tiles of a search, timed on their own: the d = 3 FP32 debug
+ * kernel first runs the search while each wavefront records the reference
+ * leaves it evaluates (BaseCase, Algorithm 2, with the k-list inserts and
+ * bound refreshes), then a second launch evaluates exactly those leaves in
+ * the same order without the walk and Score, and returns the same answer.
+ * *ms_search / *ms_replay (host): device time of the two launches;
+ * *pairs (host): point pairs evaluated (the same in both).  idx_out,
+ * dist_out as knn_search (from the replay).  Domain as knn_debug_search_log;
+ * KNN_E_UNSUPPORTED if a wavefront evaluates more than 512 leaves. */
+knn_status knn_debug_tile_replay(const knn_tree *ref, const knn_tree *query, int32_t k,
+                                 const knn_opts *opts, int64_t *idx_out, float *dist_out,
+                                 float *ms_search, float *ms_replay, int64_t *pairs,
+                                 void *stream);
+
 /* knn_search with its traversal instrumented, for checking the correctness
  * argument of the k-NN Score (Section "k-Nearest Neighbor Search", the
  * argument after Algorithm 3: the bound B(N_q) never falls below the largest

@@ -257,13 +257,19 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     uint32_t *wlog = nullptr;
 
     if (dbg) {
-        unsigned int *cnt = nullptr;
-        KNN_HIP(sc.get(&cnt, 1));
-        KNN_HIP(zero_words(cnt, 1, s));
-        a.dbg_log = dbg->log;
-        a.dbg_count = cnt;
-        a.dbg_cap = int(std::min<int64_t>(dbg->cap, INT32_MAX));
+        if (dbg->log) {
+            unsigned int *cnt = nullptr;
+            KNN_HIP(sc.get(&cnt, 1));
+            KNN_HIP(zero_words(cnt, 1, s));
+            a.dbg_log = dbg->log;
+            a.dbg_count = cnt;
+            a.dbg_cap = int(std::min<int64_t>(dbg->cap, INT32_MAX));
+        }
         a.far_first = dbg->far_first;
+        a.tile_log = dbg->tile_log;
+        a.tile_cnt = dbg->tile_cnt;
+        a.tile_cap = dbg->tile_cap;
+        a.tile_replay = dbg->tile_replay;
     }
     if (wlog_path) {
         KNN_HIP(sc.get(&wlog, size_t(grid) * 4 * 8));
@@ -322,10 +328,14 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
         KNN_HIP(hipMemcpyAsync(hst, dstats, sizeof(hst), hipMemcpyDeviceToHost, s));
     if (fb_count) KNN_HIP(hipMemcpyAsync(&hfb, fb_count, sizeof(int), hipMemcpyDeviceToHost, s));
     unsigned int hdbg = 0;
-    if (dbg)
+    if (dbg && a.dbg_count)
         KNN_HIP(hipMemcpyAsync(&hdbg, a.dbg_count, sizeof(hdbg), hipMemcpyDeviceToHost, s));
     KNN_HIP(hipStreamSynchronize(s));
-    if (dbg) dbg->n_records = int64_t(hdbg);
+    if (dbg) {
+        dbg->n_records = int64_t(hdbg);
+        dbg->ms_kernel = 0.f;
+        if (timing) (void)hipEventElapsedTime(&dbg->ms_kernel, ev[0], ev[1]);
+    }
     if (wlog) {
         std::vector<uint32_t> h(size_t(grid) * 32);
         KNN_HIP(hipMemcpy(h.data(), wlog, h.size() * 4, hipMemcpyDeviceToHost));
@@ -518,6 +528,59 @@ knn_status knn_debug_search_log(const knn_tree *ref, const knn_tree *query, int3
     knn_status st = search(ref, query, k, opts, idx_out, dist_out, (hipStream_t)stream, &dbg);
     *n_records = dbg.n_records;
     return st;
+}
+
+knn_status knn_debug_tile_replay(const knn_tree *ref, const knn_tree *query, int32_t k,
+                                 const knn_opts *opts_in, int64_t *idx_out, float *dist_out,
+                                 float *ms_search, float *ms_replay, int64_t *pairs,
+                                 void *stream) {
+    set_error("");
+    if (!ref || !ms_search || !ms_replay || !pairs)
+        return fail(KNN_E_INVALID_ARG, "knn_debug_tile_replay: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    knn_opts opts;
+    knn_opts_default(&opts);
+    if (opts_in) opts = *opts_in;
+    knn_stats st{};
+    opts.stats = &st;
+    const knn_tree *qt = query ? query : ref;
+    constexpr int kCap = 512;  // tiles per wave (the heaviest waves of the
+                               // 1M x 1M d = 3 search take about 130)
+    const size_t slots = size_t(qt->n_leaves);  // at least one per wave
+    uint32_t *tlog = nullptr, *tcnt = nullptr;
+    KNN_HIP(alloc_async(&tlog, slots * kCap, s));
+    KNN_HIP(alloc_async(&tcnt, slots, s));
+    struct Guard {
+        hipStream_t s;
+        void *a, *b;
+        ~Guard() {
+            free_async(a, s);
+            free_async(b, s);
+        }
+    } guard{s, tlog, tcnt};
+    DebugReq rec{0, nullptr, 0, 0};
+    rec.tile_log = tlog;
+    rec.tile_cnt = tcnt;
+    rec.tile_cap = kCap;
+    KNN_TRY(search(ref, query, k, &opts, idx_out, dist_out, s, &rec));
+    *ms_search = rec.ms_kernel;
+    *pairs = st.pairs;
+    std::vector<uint32_t> cnt(slots);
+    KNN_HIP(hipMemcpy(cnt.data(), tcnt, slots * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    // waves past the last query leaf never wrote a count: only the first
+    // ceil(leaves / leaves per wave) entries are read
+    const int max_leaf = int((qt->n + qt->n_leaves - 1) / qt->n_leaves);
+    int lg = 3;
+    while ((1 << lg) < max_leaf) ++lg;
+    const size_t waves = (slots + (64 >> lg) - 1) / (64 >> lg);
+    for (size_t w = 0; w < waves; ++w)
+        if (cnt[w] > uint32_t(kCap))
+            return fail(KNN_E_UNSUPPORTED, "knn_debug_tile_replay: a wave evaluated more than 512 tiles");
+    DebugReq rep = rec;
+    rep.tile_replay = 1;
+    KNN_TRY(search(ref, query, k, &opts, idx_out, dist_out, s, &rep));
+    *ms_replay = rep.ms_kernel;
+    return KNN_OK;
 }
 
 knn_status knn_search_points(const knn_tree *ref, const float *queries, int64_t n_q, int32_t k,

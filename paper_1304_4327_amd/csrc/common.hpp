@@ -162,9 +162,14 @@ knn_status all_knn(const float *ref_points, int64_t n_ref, const float *query_po
 // debug requests of knn_debug_search_log: visit order and the Score log
 struct DebugReq {
     int far_first;
-    uint32_t *log;       // device, cap records
+    uint32_t *log;       // device, cap records, or NULL
     int64_t cap;
     int64_t n_records;   // out: records the kernel produced (may exceed cap)
+    uint32_t *tile_log = nullptr;  // device: the per-wave tile lists (see SearchArgs)
+    uint32_t *tile_cnt = nullptr;
+    int tile_cap = 0;
+    int tile_replay = 0;
+    float ms_kernel = 0.f;         // out: device time of the kernel launch
 };
 // a fixed device region the search takes its scratch from instead of the
 // allocator (knn_search_noalloc)

@@ -60,6 +60,14 @@ struct SearchArgs {
     unsigned int *dbg_count;  // records written (may exceed dbg_cap: then truncated)
     int dbg_cap;              // capacity in records
     int far_first;
+    // tile list of the debug kernel: with tile_replay == 0 each wave records
+    // the reference leaves it evaluates (tile_log[wave * tile_cap + i], the
+    // count in tile_cnt[wave]); with tile_replay == 1 it evaluates exactly
+    // those leaves in that order, without the walk
+    uint32_t *tile_log;
+    uint32_t *tile_cnt;
+    int tile_cap;
+    int tile_replay;
 };
 
 // Score-log record: node, kept (1/0), first query leaf of the wave, number

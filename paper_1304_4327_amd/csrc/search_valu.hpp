@@ -71,8 +71,9 @@ __device__ inline double d2_fp64(const float (&q)[D], const float *r) {
     return s;
 }
 
-// DBG: the debug form (Score log, visit-order switch); the search kernels
-// are built with DBG = false, which compiles both out
+// DBG: the debug form (Score log, visit-order switch, tile list record and
+// replay); the search kernels are built with DBG = false, which compiles all
+// of it out
 template <int D, int K, int LG, bool DBG = false>
 __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     constexpr int DP = stride_for(D);
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
                 bg[g] = g < NG ? __builtin_bit_cast(float, __builtin_amdgcn_readlane(
                                                               __builtin_bit_cast(int, bound2), g << lpl_log2))
                                : 0.f;
-            if (lane == 0) {
+            if (lane == 0 && a.dbg_count) {
                 const unsigned r = atomicAdd(a.dbg_count, 1u);
                 if (int(r) < a.dbg_cap) {
                     uint32_t *rec = a.dbg_log + int64_t(r) * kDbgWords;
@@ -378,8 +379,17 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         refresh_bound();
     };
 
+    // debug form: replay of a recorded tile list instead of the walk
+    bool replay = false;
+    if constexpr (DBG) {
+        replay = a.tile_replay != 0;
+        if (replay) {
+            const int nt = uniform_i(int(a.tile_cnt[wave]));
+            for (int i = 0; i < nt; ++i) tile(uniform_i(int(a.tile_log[int64_t(wave) * a.tile_cap + i])));
+        }
+    }
     // ---- stackless depth-first walk, nearer child first ---------------------
-    {
+    if (!replay) {
         float dm0, dm1;
         int node = 0, depth = 0;
         uint64_t nearbits = 0;
@@ -433,9 +443,16 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
                     }
                 }
                 if (!leaf) break;
+                if constexpr (DBG) {
+                    if (a.tile_log && lane == 0 && int(n_tiles) < a.tile_cap)
+                        a.tile_log[int64_t(wave) * a.tile_cap + n_tiles] = uint32_t(node);
+                }
                 tile(node);
                 down = false;
             }
+        }
+        if constexpr (DBG) {
+            if (a.tile_log && lane == 0) a.tile_cnt[wave] = n_tiles;
         }
     }
 

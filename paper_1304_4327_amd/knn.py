@@ -119,6 +119,10 @@ _SIGS = {
     "knn_debug_search_log": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts),
                                             ctypes.c_int32, _P, ctypes.c_int64,
                                             ctypes.POINTER(ctypes.c_int64), _P, _P, _P]),
+    "knn_debug_tile_replay": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts),
+                                             _P, _P, ctypes.POINTER(ctypes.c_float),
+                                             ctypes.POINTER(ctypes.c_float),
+                                             ctypes.POINTER(ctypes.c_int64), _P]),
     "knn_debug_bf16_tiles": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P,
                                             _P, _P]),
 }
@@ -625,3 +629,17 @@ def knn_debug_search_log(ref: Tree, query: Tree | None, k: int, bound="B", exclu
                                        ctypes.c_void_p(dist.data_ptr()), _stream(stream)))
     kept = min(n.value, capacity)
     return idx, dist, log[:kept].cpu().numpy().view(np.uint32), n.value
+
+
+def knn_debug_tile_replay(ref: Tree, query: Tree | None, k: int, exclude_self=False, stream=None):
+    """The search's BaseCase tiles replayed without the walk (d = 3 FP32).
+    Returns (idx, dist, ms_search, ms_replay, pairs)."""
+    nq = (query or ref).n
+    idx, dist = _outputs(None, nq, k)
+    ms_s, ms_r, pairs = ctypes.c_float(), ctypes.c_float(), ctypes.c_int64()
+    o, _ = _make_opts("B", "fp32", exclude_self, None, None, False)
+    _check(load().knn_debug_tile_replay(ref.handle, query.handle if query is not None else None,
+                                        int(k), ctypes.byref(o), ctypes.c_void_p(idx.data_ptr()),
+                                        ctypes.c_void_p(dist.data_ptr()), ctypes.byref(ms_s),
+                                        ctypes.byref(ms_r), ctypes.byref(pairs), _stream(stream)))
+    return idx, dist, ms_s.value, ms_r.value, pairs.value

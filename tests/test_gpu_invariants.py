@@ -91,3 +91,18 @@ def test_debug_kernel_rejects_other_domains():
     with pytest.raises(knn.KnnError) as e:
         knn.knn_debug_search_log(rt, None, 5, exclude_self=True)
     assert e.value.status == knn.KNN_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("name,scale", [("uniform10k_d3_k5", 1.0), ("gmm1m_d3_k10", 0.05)])
+def test_tile_replay_reproduces_the_search(name, scale):
+    """The tile replay evaluates the recorded leaves in the recorded order, so
+    its lists equal the search's bit for bit (and the oracle's)."""
+    import torch
+    from paper_1304_4327_amd import knn
+    ref, q, k, leaf = datagen.make(name, scale=scale)
+    rt = knn.knn_build_tree(torch.from_numpy(ref).cuda(), leaf)
+    qt = None if q is None else knn.knn_build_tree(torch.from_numpy(q).cuda(), leaf)
+    idx, dist, ms_s, ms_r, pairs = knn.knn_debug_tile_replay(rt, qt, k, exclude_self=q is None)
+    want = knn.knn_search(rt, qt, k, exclude_self=q is None, stats=True)
+    assert torch.equal(idx, want[0]) and torch.equal(dist, want[1])
+    assert pairs == want[2]["pairs"] and 0 < ms_r and 0 < ms_s
