@@ -9,12 +9,12 @@
 namespace knnx {
 hipError_t launch_search_valu_debug_d3(const SearchArgs &a, int K, int grid, hipStream_t s) {
     switch (K) {
-        case 4: return launch_search_valu_k<3, 4, true>(a, grid, s);
-        case 5: return launch_search_valu_k<3, 5, true>(a, grid, s);
-        case 8: return launch_search_valu_k<3, 8, true>(a, grid, s);
-        case 10: return launch_search_valu_k<3, 10, true>(a, grid, s);
-        case 11: return launch_search_valu_k<3, 11, true>(a, grid, s);
-        case 16: return launch_search_valu_k<3, 16, true>(a, grid, s);
+        case 4: return launch_search_valu_k<3, 4, kValuDebug>(a, grid, s);
+        case 5: return launch_search_valu_k<3, 5, kValuDebug>(a, grid, s);
+        case 8: return launch_search_valu_k<3, 8, kValuDebug>(a, grid, s);
+        case 10: return launch_search_valu_k<3, 10, kValuDebug>(a, grid, s);
+        case 11: return launch_search_valu_k<3, 11, kValuDebug>(a, grid, s);
+        case 16: return launch_search_valu_k<3, 16, kValuDebug>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

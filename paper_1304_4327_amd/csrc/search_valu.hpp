@@ -25,8 +25,7 @@
 //        B2 = min over the leaf's queries of D_p[k] + 2 lambda    (rho = lambda)
 //        BP = min over the queries of an ancestor + 2 lambda(anc) (B(Par))
 //        B  = min(B1, B2, BP)
-//     (the seeded kernel in search_valu_seeded.hpp adds the seed radius to
-//     the min) and a node is pruned when d_min^2 > B^2 (1 + 2^-16).
+//     and a node is pruned when d_min^2 > B^2 (1 + 2^-16).
 //   * all-kNN of a set on itself keeps k+1 entries per list; the query's own
 //     point (distance 0) takes one of them and is dropped at write-out, so no
 //     per-pair index test is needed.
@@ -37,6 +36,18 @@
 // error (d+2) u can exceed the 1e-6 relative acceptance window at high d.
 // The final k entries are always re-scored in FP64 and sorted by
 // (distance, original index).
+//
+// Three forms of one kernel, chosen at compile time (MODE):
+//   * kValuPlain: the search;
+//   * kValuDebug: every Score call logged with each leaf's bound, the walk
+//     optionally farther child first, and the BaseCase leaves of each wave
+//     recorded or replayed without the walk;
+//   * kValuSeeded: a seed radius (not in the paper; only an initial value of
+//     a query leaf's pruning bound) joins the minimum of the leaf bound, and
+//     a leaf whose k-th distances exceed its seed is searched again inside
+//     the same wave, from empty lists, with the proven bound of the first
+//     pass.
+// The plain form carries none of the other two forms' state.
 #pragma once
 
 #include "search.hpp"
@@ -71,11 +82,12 @@ __device__ inline double d2_fp64(const float (&q)[D], const float *r) {
     return s;
 }
 
-// DBG: the debug form (Score log, visit-order switch, tile list record and
-// replay); the search kernels are built with DBG = false, which compiles all
-// of it out
-template <int D, int K, int LG, bool DBG = false>
+enum : int { kValuPlain = 0, kValuDebug = 1, kValuSeeded = 2 };
+
+template <int D, int K, int LG, int MODE = kValuPlain>
 __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
+    constexpr bool DBG = MODE == kValuDebug;
+    constexpr bool SEEDED = MODE == kValuSeeded;
     constexpr int DP = stride_for(D);
     constexpr bool RESCORE = D > 8;
     constexpr float kInf = __builtin_inff();
@@ -102,7 +114,8 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     const int qleaf = has_leaf ? slot : 0;
     const int qnode = a.q_first_leaf + qleaf;
     const int2 qr = has_leaf ? a.qrange[qnode] : make_int2(0, 0);
-    const bool valid = has_leaf && li < qr.y;
+    const bool valid0 = has_leaf && li < qr.y;  // this lane holds a query point
+    bool valid = valid0;  // ... that the current pass searches
     const int qpos = qr.x + li;
     const int kk = a.k + (a.self ? 1 : 0);  // list length (self match included)
 
@@ -146,6 +159,10 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         uhi[0] = hi;
     }
     const float lam2 = has_leaf ? 2.0f * a.qlam[qnode] : 0.f;
+    // seeded form: a seed is only a pruning radius; NaN or negative values
+    // prune everything and send the leaf to the second pass
+    const float seed = (SEEDED && a.seed && has_leaf) ? fmaxf(a.seed[qleaf], 0.0f) : kInf;
+    float seed2 = seed * seed;
 
     float dist[K];
     int idx[K];
@@ -154,10 +171,10 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         dist[j] = (j < K - kk) ? -kInf : kInf;
         idx[j] = -1;
     }
-    float bound2 = kInf;
+    float bound2 = (!SEEDED || a.bound == KNN_BOUND_NONE) ? kInf : seed2;
     uint32_t n_score = 0, n_tiles = 0, n_ins = 0, n_pass = 0;
     uint64_t n_pairs = 0;
-    const int n_valid = __popcll(ballot(valid));
+    int n_valid = __popcll(ballot(valid));
 
     // Prefetch into the scalar cache: a few scalar loads of lines that the
     // next steps will read, issued together with loads that are waited for
@@ -311,7 +328,7 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
                 }
             }
         }
-        bound2 = b;
+        bound2 = SEEDED ? fminf(b, seed2) : b;
     };
 
     // BaseCase over one reference leaf: every lane against each reference
@@ -389,72 +406,123 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         }
     }
     // ---- stackless depth-first walk, nearer child first ---------------------
-    if (!replay) {
-        float dm0, dm1;
-        int node = 0, depth = 0;
-        uint64_t nearbits = 0;
-        bool down = score(0, dm0);
-        if (down) {
-            // outer loop: one reference leaf per iteration; the inner walk
-            // leaves the k-lists untouched, so they are not carried through
-            // its loop (carried through one loop with the tile, the compiler
-            // moved every list register on every walk step)
-            for (;;) {
-                bool leaf = false;
+    // Seeded form: a second pass follows in the same wave.  Leaves with a
+    // query whose k-th distance exceeds its seed are searched again from empty
+    // lists, with the proven B2 bound of the first pass as initial bound and
+    // no seed; the other leaves' lanes sit out (their lists are final).  The
+    // second pass of a few leaves then runs beside the other waves instead of
+    // as a launch of its own.
+    uint32_t s_score = 0, s_tiles = 0;  // first-pass counts
+    uint64_t s_pairs = 0;
+    int s_ins = 0;
+    bool fb_q = false, fb_leaf = false;  // this lane's query / leaf missed its seed
+    bool second = false;                 // a second pass ran in this wave
+    // (a loop of at most two passes around the walk: as a closure called
+    // twice, the walk made the kernel much slower)
+    for (int pass = 0;; ++pass) {
+        if (!replay) {
+            float dm0, dm1;
+            int node = 0, depth = 0;
+            uint64_t nearbits = 0;
+            bool down = score(0, dm0);
+            if (down) {
+                // outer loop: one reference leaf per iteration; the inner walk
+                // leaves the k-lists untouched, so they are not carried through
+                // its loop (carried through one loop with the tile, the compiler
+                // moved every list register on every walk step)
                 for (;;) {
-                    if (down) {
-                        if (node >= a.r_first_leaf) {
-                            leaf = true;
-                            break;
-                        }
-                        const int c0 = 2 * node + 1, c1 = c0 + 1;
-                        bool k0, k1;
-                        score_children(c0, k0, k1, dm0, dm1);
-                        if (!k0 && !k1) {
-                            down = false;
-                            continue;
-                        }
-                        bool right = k1 && (!k0 || dm1 < dm0);
-                        if constexpr (DBG) {
-                            // farther child first: the other visit order
-                            if (a.far_first) right = k1 && (!k0 || dm1 > dm0);
-                        }
-                        if (right)
-                            nearbits |= (uint64_t(1) << depth);
-                        else
-                            nearbits &= ~(uint64_t(1) << depth);
-                        node = uniform_i(right ? c1 : c0);
-                        ++depth;
-                    } else {
-                        if (node == 0) break;
-                        --depth;
-                        const bool is_right = (node & 1) == 0;
-                        const bool near_right = (nearbits >> depth) & 1;
-                        if (is_right == near_right) {
-                            const int far = is_right ? node - 1 : node + 1;
-                            if (score(far, dm0)) {
-                                node = far;
-                                ++depth;
-                                down = true;
+                    bool leaf = false;
+                    for (;;) {
+                        if (down) {
+                            if (node >= a.r_first_leaf) {
+                                leaf = true;
+                                break;
+                            }
+                            const int c0 = 2 * node + 1, c1 = c0 + 1;
+                            bool k0, k1;
+                            score_children(c0, k0, k1, dm0, dm1);
+                            if (!k0 && !k1) {
+                                down = false;
                                 continue;
                             }
+                            bool right = k1 && (!k0 || dm1 < dm0);
+                            if constexpr (DBG) {
+                                // farther child first: the other visit order
+                                if (a.far_first) right = k1 && (!k0 || dm1 > dm0);
+                            }
+                            if (right)
+                                nearbits |= (uint64_t(1) << depth);
+                            else
+                                nearbits &= ~(uint64_t(1) << depth);
+                            node = uniform_i(right ? c1 : c0);
+                            ++depth;
+                        } else {
+                            if (node == 0) break;
+                            --depth;
+                            const bool is_right = (node & 1) == 0;
+                            const bool near_right = (nearbits >> depth) & 1;
+                            if (is_right == near_right) {
+                                const int far = is_right ? node - 1 : node + 1;
+                                if (score(far, dm0)) {
+                                    node = far;
+                                    ++depth;
+                                    down = true;
+                                    continue;
+                                }
+                            }
+                            node = uniform_i((node - 1) >> 1);
                         }
-                        node = uniform_i((node - 1) >> 1);
                     }
+                    if (!leaf) break;
+                    if constexpr (DBG) {
+                        if (a.tile_log && lane == 0 && int(n_tiles) < a.tile_cap)
+                            a.tile_log[int64_t(wave) * a.tile_cap + n_tiles] = uint32_t(node);
+                    }
+                    tile(node);
+                    down = false;
                 }
-                if (!leaf) break;
-                if constexpr (DBG) {
-                    if (a.tile_log && lane == 0 && int(n_tiles) < a.tile_cap)
-                        a.tile_log[int64_t(wave) * a.tile_cap + n_tiles] = uint32_t(node);
-                }
-                tile(node);
-                down = false;
+            }
+            if constexpr (DBG) {
+                if (a.tile_log && lane == 0) a.tile_cnt[wave] = n_tiles;
             }
         }
-        if constexpr (DBG) {
-            if (a.tile_log && lane == 0) a.tile_cnt[wave] = n_tiles;
+        if constexpr (!SEEDED) {
+            break;
+        } else {
+            if (pass > 0) break;
+            // seed check on the list (FP32 squared distances: their error is
+            // far inside the check's factor)
+            fb_q = valid && !(dist[K - 1] <= seed2 * (1.0f - 0x1p-18f));
+            if (!ballot(fb_q)) break;
+            float f = fb_q ? 1.0f : 0.0f;
+            for (int l = 0; l < lpl_log2; ++l) f = xor_level(f, l, OpMax());
+            fb_leaf = valid && f > 0.0f;
+            // proven bound for the leaf: min over its full lists of D_p[k]
+            // plus 2 lambda (the B2 argument holds whatever seed built the
+            // lists)
+            float kb = (valid && dist[K - 1] < kInf) ? __builtin_amdgcn_sqrtf(dist[K - 1]) : kInf;
+            for (int l = 0; l < lpl_log2; ++l) kb = xor_level(kb, l, OpMin());
+            const float pb = (kb + lam2) * (1.0f + 0x1p-18f);
+            second = true;
+            s_score = n_score;
+            s_tiles = n_tiles;
+            s_pairs = n_pairs;
+            s_ins = n_ins;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                dist[j] = fb_leaf ? ((j < K - kk) ? -kInf : kInf) : dist[j];
+                idx[j] = fb_leaf ? -1 : idx[j];
+            }
+            valid = fb_leaf;
+            n_valid = __popcll(ballot(valid));
+            // the proven bound stays in every refresh's minimum (as the seed
+            // term did in the first pass): the fresh lists give B1 = +inf
+            // until they fill
+            seed2 = (a.bound == KNN_BOUND_NONE || !fb_leaf) ? kInf : pb * pb;
+            bound2 = seed2;
         }
     }
+    valid = valid0;
 
     // keeps the prefetch loads (k >= 1 always)
     if ((tacc ^ q0 ^ q1 ^ q2) == 0x7fc00001u && a.k < 0) a.out_idx[0] = 0;
@@ -486,13 +554,20 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
             }
         }
     }
-    // largest k-th distance of the leaf
+    // largest k-th distance of the leaf; seeded form: leaves searched a
+    // second time are flagged (counted by the host)
     for (int l = 0; l < lpl_log2; ++l) worst = xor_level(worst, l, OpMax());
-    if (has_leaf && li == 0 && a.leaf_kth) a.leaf_kth[qleaf] = fmaxf(worst, 0.0f);
+    if (has_leaf && li == 0) {
+        if (a.leaf_kth) a.leaf_kth[qleaf] = fmaxf(worst, 0.0f);
+        if (SEEDED && a.fallback && fb_leaf) a.fallback[qleaf] = 1;
+    }
     if (a.wave_log || a.stats) {
-        int ins = n_ins;
+        int ins = n_ins, ins1 = second ? s_ins : n_ins;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) ins += __shfl_xor(ins, off);
+        for (int off = 32; off > 0; off >>= 1) {
+            ins += __shfl_xor(ins, off);
+            if constexpr (SEEDED) ins1 += __shfl_xor(ins1, off);
+        }
         if (a.wave_log && lane == 0) {
             uint32_t *w = a.wave_log + int64_t(wave) * 8;
             w[0] = 0;  // no clock read: a side-effecting read here would
@@ -503,7 +578,27 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
             w[4] = n_pass;
             w[5] = uint32_t(qleaf);
         }
-        if (a.stats && lane == 0) {
+        if constexpr (SEEDED) {
+            const uint64_t fbmask = ballot(fb_q);
+            if (a.stats && lane == 0) {
+                // first-pass counts, then the second pass's in the fallback
+                // block
+                const uint32_t sc1 = second ? s_score : n_score, ti1 = second ? s_tiles : n_tiles;
+                const uint64_t pa1 = second ? s_pairs : n_pairs;
+                atomicAdd(&a.stats[ST_SCORE], (unsigned long long)sc1);
+                atomicAdd(&a.stats[ST_TILES], (unsigned long long)ti1);
+                atomicAdd(&a.stats[ST_PAIRS], (unsigned long long)pa1);
+                atomicAdd(&a.stats[ST_INSERTS], (unsigned long long)ins1);
+                atomicAdd(&a.stats[ST_FB_QUERIES], (unsigned long long)__popcll(fbmask));
+                if (second) {
+                    unsigned long long *f = a.stats + ST_COUNT;
+                    atomicAdd(&f[ST_SCORE], (unsigned long long)(n_score - sc1));
+                    atomicAdd(&f[ST_TILES], (unsigned long long)(n_tiles - ti1));
+                    atomicAdd(&f[ST_PAIRS], (unsigned long long)(n_pairs - pa1));
+                    atomicAdd(&f[ST_INSERTS], (unsigned long long)(ins - ins1));
+                }
+            }
+        } else if (a.stats && lane == 0) {
             atomicAdd(&a.stats[ST_SCORE], (unsigned long long)n_score);
             atomicAdd(&a.stats[ST_TILES], (unsigned long long)n_tiles);
             atomicAdd(&a.stats[ST_PAIRS], (unsigned long long)n_pairs);
@@ -512,31 +607,33 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     }
 }
 
-template <int D, int K, bool DBG = false>
+template <int D, int K, int MODE = kValuPlain>
 hipError_t launch_search_valu_k(const SearchArgs &a, int grid, hipStream_t s) {
     switch (a.lpl_log2) {
-        case 3: k_search_valu<D, K, 3, DBG><<<grid, 256, 0, s>>>(a); break;
-        case 4: k_search_valu<D, K, 4, DBG><<<grid, 256, 0, s>>>(a); break;
-        case 5: k_search_valu<D, K, 5, DBG><<<grid, 256, 0, s>>>(a); break;
-        case 6: k_search_valu<D, K, 6, DBG><<<grid, 256, 0, s>>>(a); break;
+        case 3: k_search_valu<D, K, 3, MODE><<<grid, 256, 0, s>>>(a); break;
+        case 4: k_search_valu<D, K, 4, MODE><<<grid, 256, 0, s>>>(a); break;
+        case 5: k_search_valu<D, K, 5, MODE><<<grid, 256, 0, s>>>(a); break;
+        case 6: k_search_valu<D, K, 6, MODE><<<grid, 256, 0, s>>>(a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int D>
+// MODE kValuPlain (the search) or kValuSeeded; the debug form has its own
+// instantiation for d = 3
+template <int D, int MODE = kValuPlain>
 hipError_t launch_search_valu(const SearchArgs &a, int K, int grid, hipStream_t s) {
     switch (K) {
-        case 4: return launch_search_valu_k<D, 4>(a, grid, s);
-        case 5: return launch_search_valu_k<D, 5>(a, grid, s);
-        case 8: return launch_search_valu_k<D, 8>(a, grid, s);
-        case 10: return launch_search_valu_k<D, 10>(a, grid, s);
-        case 11: return launch_search_valu_k<D, 11>(a, grid, s);
-        case 16: return launch_search_valu_k<D, 16>(a, grid, s);
-        case 32: return launch_search_valu_k<D, 32>(a, grid, s);
-        case 50: return launch_search_valu_k<D, 50>(a, grid, s);
-        case 51: return launch_search_valu_k<D, 51>(a, grid, s);
-        case 64: return launch_search_valu_k<D, 64>(a, grid, s);
+        case 4: return launch_search_valu_k<D, 4, MODE>(a, grid, s);
+        case 5: return launch_search_valu_k<D, 5, MODE>(a, grid, s);
+        case 8: return launch_search_valu_k<D, 8, MODE>(a, grid, s);
+        case 10: return launch_search_valu_k<D, 10, MODE>(a, grid, s);
+        case 11: return launch_search_valu_k<D, 11, MODE>(a, grid, s);
+        case 16: return launch_search_valu_k<D, 16, MODE>(a, grid, s);
+        case 32: return launch_search_valu_k<D, 32, MODE>(a, grid, s);
+        case 50: return launch_search_valu_k<D, 50, MODE>(a, grid, s);
+        case 51: return launch_search_valu_k<D, 51, MODE>(a, grid, s);
+        case 64: return launch_search_valu_k<D, 64, MODE>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }
