@@ -383,6 +383,51 @@ knn_status knn_seed_features(const knn_tree *ref, const knn_tree *query, float *
 knn_status knn_seed_radius(const knn_mlp *mlp, const float *feats, int64_t n, float log_margin,
                            float *radius, void *stream);
 
+/* Options of knn_seed_train. */
+typedef struct knn_train_opts {
+    int32_t epochs;        /* passes over the training rows, >= 1               */
+    int32_t batch;         /* rows per Adam step, >= 1                          */
+    float lr;              /* Adam step size, > 0 (beta1 0.9, beta2 0.999,
+                              eps 1e-8)                                         */
+    float val_frac;        /* held-out fraction for the margin, in (0, 1)       */
+    float target_fallback; /* fraction of held-out leaves whose target may
+                              exceed the calibrated radius, in [0, 1)           */
+    uint64_t seed;         /* random streams of the split, the initial
+                              weights and the batch orders                      */
+} knn_train_opts;
+
+/* Trains a new seed network on the GPU from n (features, target) rows, the
+ * targets being each query leaf's largest k-th neighbour distance from a
+ * plain search (knn_search's leaf_kth_out; the network learns its log).
+ * feats: device, n x n_in (knn_seed_features rows); kth: device, n.
+ * Steps, all on the device except the two sorts of random keys and the
+ * quantile of the held-out residuals (host, O(n log n)):
+ *   1. split: the rows ordered by random key; the first
+ *      max(1, floor(n * val_frac)) are held out, the rest train;
+ *   2. standardisation: mean and (population) deviation of every training
+ *      column in FP64 (a deviation below 1e-12 counts as 1); targets
+ *      t = (log max(kth, 1e-30) - y_mu) / y_sd;
+ *   3. weights uniform in +-sqrt(6 / fan_in), biases 0;
+ *   4. each epoch: the training rows in a fresh random-key order, cut into
+ *      batches of `batch` rows (the last one shorter); per batch the mean
+ *      squared error gradient (knn_mlp_loss_grad) and one Adam step;
+ *   5. log_margin: the (1 - target_fallback) quantile (linear between order
+ *      statistics) of the held-out residuals log kth - (y * y_sd + y_mu).
+ * Random numbers: SplitMix64 (Steele, Lea and Flood, 2014) in counter form,
+ * value(s, i) = mix(s + (i + 1) * 0x9E3779B97F4A7C15) mod 2^64; stream p
+ * (0 weights, 1 split, 2 + e epoch e) has seed value(seed, p); a key is the
+ * stream's i-th value (ties broken by row), a uniform is its top 53 bits
+ * times 2^-53.
+ * Outputs: *out a new network (free with knn_mlp_free) with the
+ * standardisation set; *log_margin_out (host); loss_out (host, optional,
+ * `epochs` floats): mean batch loss of each epoch.
+ * Domain: n >= 2, 1 <= n_in <= 72, kth finite and >= 0 (else
+ * KNN_E_INVALID_ARG, checked on the device copy before training).
+ * Errors: KNN_E_INVALID_ARG, KNN_E_OOM, KNN_E_DEVICE. */
+knn_status knn_seed_train(const float *feats, const float *kth, int64_t n, int32_t n_in,
+                          const knn_train_opts *opts, knn_mlp **out, float *log_margin_out,
+                          float *loss_out, void *stream);
+
 /* ------------------------------------------------------------------------
  * Test exports.  They run pieces of the search kernels on inputs the caller
  * chooses, so that tests can check them against the paper's definitions.

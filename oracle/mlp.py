@@ -83,3 +83,100 @@ def adam_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mhat = m / (1.0 - beta1 ** t)
     vhat = v / (1.0 - beta2 ** t)
     return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+# ---- training procedure --------------------------------------------------
+# The steps of the library's seed training, in FP64, with the random numbers
+# drawn from SplitMix64 (Steele, Lea and Flood, 2014) in counter form:
+# value(s, i) = mix(s + (i + 1) * 0x9E3779B97F4A7C15) mod 2^64; stream p
+# (0 weights, 1 split, 2 + e epoch e) is seeded with value(seed, p).
+
+_GOLDEN = 0x9E3779B97F4A7C15
+_MASK = (1 << 64) - 1
+
+
+def splitmix_values(s: int, count: int) -> np.ndarray:
+    """Values 0 .. count-1 of the SplitMix64 sequence that starts at state s
+    (Python integers, exact modulo 2^64)."""
+    out = np.empty(count, np.uint64)
+    for i in range(count):
+        z = (s + (i + 1) * _GOLDEN) & _MASK
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK
+        out[i] = z ^ (z >> 31)
+    return out
+
+
+def splitmix_value(s: int, i: int) -> int:
+    return int(splitmix_values((s + i * _GOLDEN) & _MASK, 1)[0])
+
+
+def key_order(s: int, n: int) -> np.ndarray:
+    """Rows 0 .. n-1 ordered by (key, row), key i = value i of stream s."""
+    keys = splitmix_values(s, n)
+    return np.lexsort((np.arange(n), keys))
+
+
+def init_params(n_in: int, H: int, seed: int) -> np.ndarray:
+    """Weights uniform in +-sqrt(6 / fan_in) from stream 0 (one counter over
+    W1, W2, w3 in that order), biases zero; FP32 values as the library
+    stores them."""
+    s0 = splitmix_value(seed, 0)
+    n_w = H * n_in + H * H + H
+    u = (splitmix_values(s0, n_w) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    parts, at = [], 0
+    for fan_out, fan_in in ((H, n_in), (H, H), (1, H)):
+        a = np.sqrt(6.0 / fan_in)
+        parts.append((-a + 2.0 * a * u[at:at + fan_out * fan_in]).astype(np.float32))
+        parts.append(np.zeros(fan_out, np.float32))
+        at += fan_out * fan_in
+    return np.concatenate(parts).astype(np.float64)
+
+
+def train(feats, kth, epochs, batch, lr, val_frac, target_fallback, seed, H=64):
+    """The seed training in FP64.  Returns (params, mu, inv_sd, y_mu, y_sd,
+    log_margin, per-epoch mean losses).
+
+    1. rows ordered by random key (stream 1): the first max(1, floor(n *
+       val_frac)) are held out;
+    2. mean and population deviation of every training column (deviation
+       below 1e-12 counts as 1), targets t = (log max(kth, 1e-30) - y_mu) /
+       y_sd;
+    3. initial weights from stream 0;
+    4. each epoch e: training rows in the key order of stream 2 + e, cut into
+       batches; mean squared error gradient and one Adam step per batch;
+    5. log margin: the (1 - target_fallback) quantile, linear between order
+       statistics, of the held-out residuals log kth - (y * y_sd + y_mu).
+    """
+    x = np.asarray(feats, np.float64)
+    y = np.log(np.maximum(np.asarray(kth, np.float64), 1e-30))
+    n, n_in = x.shape
+    n_val = max(1, int(np.floor(n * val_frac)))
+    order = key_order(splitmix_value(seed, 1), n)
+    va, tr = order[:n_val], order[n_val:]
+    xtr, ytr = x[tr], y[tr]
+    mu = xtr.mean(axis=0)
+    sd = xtr.std(axis=0)
+    sd[sd < 1e-12] = 1.0
+    y_mu, y_sd = float(ytr.mean()), max(float(ytr.std()), 1e-12)
+    t = (ytr - y_mu) / y_sd
+    inv_sd = 1.0 / sd
+    p = init_params(n_in, H, seed)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    step = 0
+    history = []
+    for e in range(epochs):
+        o = key_order(splitmix_value(seed, 2 + e), len(tr))
+        losses = []
+        for b0 in range(0, len(tr), batch):
+            bi = o[b0:b0 + batch]
+            L, g = loss_and_grad(p, xtr[bi], t[bi], mu, inv_sd, n_in, H)
+            step += 1
+            p, m, v = adam_step(p, g, m, v, step, lr)
+            losses.append(L)
+        history.append(float(np.mean(losses)))
+    pred = forward(p, x[va], mu, inv_sd, n_in, H) * y_sd + y_mu
+    resid = y[va] - pred
+    margin = float(np.quantile(resid, 1.0 - target_fallback))
+    return p, mu, inv_sd, y_mu, y_sd, margin, history

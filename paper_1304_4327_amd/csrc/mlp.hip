@@ -14,12 +14,18 @@
 //   k_seed_features per query leaf: box centre, lambda, point count, log
 //                   density of the reference leaf reached from the centre
 //   k_seed_radius   exp(y * y_sd + y_mu + log_margin)
+//   k_train_*       training-set preparation for knn_seed_train: log
+//                   targets, row gathers, FP64 column mean and deviation,
+//                   standardised targets
 // Parameter layout: W1 (H x n_in, row-major), b1, W2 (H x H), b2, w3 (H), b3.
 #include "search.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
+#include <utility>
 #include <vector>
 
 namespace knnx {
@@ -262,6 +268,69 @@ __global__ void k_seed_radius(const float *__restrict__ yraw, int64_t n, float y
     if (i < n) radius[i] = expf(yraw[i] * y_sd + y_mu + log_margin);
 }
 
+// ---- training-set preparation ---------------------------------------------
+// y[i] = log max(kth[i], 1e-30); bad = 1 when kth[i] is negative or not finite
+__global__ void k_train_log_targets(const float *__restrict__ kth, int64_t n, float *__restrict__ y,
+                                    int *__restrict__ bad) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float v = kth[i];
+    if (!(v >= 0.f) || !isfinite(v)) *bad = 1;
+    y[i] = float(log(fmax(double(v), 1e-30)));
+}
+
+// rows idx[0 .. n) of x (n_in columns) and of y, in that order
+__global__ void k_train_gather(const float *__restrict__ x, const float *__restrict__ y,
+                               const int32_t *__restrict__ idx, int64_t n, int n_in,
+                               float *__restrict__ xo, float *__restrict__ yo) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t r = idx[i];
+    for (int j = 0; j < n_in; ++j) xo[i * n_in + j] = x[r * n_in + j];
+    yo[i] = y[r];
+}
+
+// FP64 sum of a block's values (fixed order: strided per thread, then a tree)
+__device__ inline double block_sum(double v, double *red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// one block per column c of x (n rows, row stride ld): out[2c] = mean,
+// out[2c + 1] = population deviation, both in FP64 (two passes)
+__global__ __launch_bounds__(256) void k_train_column_stats(const float *__restrict__ x, int64_t n,
+                                                            int ld, double *__restrict__ out) {
+    __shared__ double red[256];
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += double(x[i * ld + c]);
+    const double mean = block_sum(s, red) / double(n);
+    double q = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double t = double(x[i * ld + c]) - mean;
+        q = fma(t, t, q);
+    }
+    const double var = block_sum(q, red) / double(n);
+    if (threadIdx.x == 0) {
+        out[2 * c] = mean;
+        out[2 * c + 1] = sqrt(var);
+    }
+}
+
+// t[i] = (y[i] - mu) / sd
+__global__ void k_train_standardise(const float *__restrict__ y, int64_t n, double mu, double sd,
+                                    float *__restrict__ t) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) t[i] = float((double(y[i]) - mu) / sd);
+}
+
 }  // namespace knnx
 
 // ---------------------------------------------------------------------------
@@ -286,8 +355,8 @@ namespace {
 
 knn_status ensure_grad_scratch(knn_mlp *m, int64_t nblk) {
     if (nblk > m->partial_blocks) {
-        hipFree(m->partial);
-        hipFree(m->lossbuf);
+        (void)hipFree(m->partial);
+        (void)hipFree(m->lossbuf);
         m->partial = nullptr;
         m->lossbuf = nullptr;
         KNN_HIP(hipMalloc(&m->partial, size_t(nblk) * m->P * sizeof(float)));
@@ -298,6 +367,64 @@ knn_status ensure_grad_scratch(knn_mlp *m, int64_t nblk) {
 }
 
 MlpDev dev_of(const knn_mlp *m) { return MlpDev{m->p, m->mu, m->isd, m->n_in}; }
+
+// gradient of the mean squared error over n rows into m->g, the loss into
+// m->lossbuf[0] (no synchronisation)
+knn_status launch_loss_grad(knn_mlp *m, const float *x, const float *t, int64_t n, hipStream_t s) {
+    const int64_t nblk = (n + kGradBlock - 1) / kGradBlock;
+    KNN_TRY(ensure_grad_scratch(m, nblk));
+    k_mlp_grad<<<int(nblk), kGradBlock, 0, s>>>(dev_of(m), x, t, n, m->partial, m->lossbuf + 1);
+    k_mlp_reduce<<<int((m->P + 255) / 256), 256, 0, s>>>(m->partial, int(nblk), int(m->P), m->g,
+                                                         m->lossbuf + 1, m->lossbuf,
+                                                         1.0f / float(n));
+    KNN_HIP(hipGetLastError());
+    return KNN_OK;
+}
+
+// one Adam step with the stored gradient (no synchronisation)
+knn_status launch_adam(knn_mlp *m, float lr, float beta1, float beta2, float eps, hipStream_t s) {
+    m->step += 1;
+    const float c1 = float(1.0 - std::pow(double(beta1), double(m->step)));
+    const float c2 = float(1.0 - std::pow(double(beta2), double(m->step)));
+    k_mlp_adam<<<int((m->P + 255) / 256), 256, 0, s>>>(m->p, m->g, m->m, m->v, int(m->P), lr, beta1,
+                                                       beta2, eps, c1, c2);
+    KNN_HIP(hipGetLastError());
+    return KNN_OK;
+}
+
+// device buffers of one call, released in stream order on every return
+struct CallBufs {
+    hipStream_t s;
+    std::vector<void *> ps;
+    ~CallBufs() {
+        for (void *p : ps) free_async(p, s);
+    }
+    template <class T>
+    hipError_t get(T **p, size_t count) {
+        const hipError_t e = alloc_async(p, count, s);
+        if (e == hipSuccess) ps.push_back(*p);
+        return e;
+    }
+};
+
+// SplitMix64 (Steele, Lea and Flood, 2014) in counter form: the i-th value of
+// the sequence started at state s
+uint64_t splitmix_value(uint64_t s, uint64_t i) {
+    uint64_t z = s + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// rows 0 .. n-1 ordered by (key, row), key i = value i of stream s
+std::vector<int32_t> key_order(uint64_t s, int64_t n) {
+    std::vector<std::pair<uint64_t, int32_t>> kv(static_cast<size_t>(n));
+    for (int64_t i = 0; i < n; ++i) kv[size_t(i)] = {splitmix_value(s, uint64_t(i)), int32_t(i)};
+    std::sort(kv.begin(), kv.end());
+    std::vector<int32_t> o(static_cast<size_t>(n));
+    for (int64_t i = 0; i < n; ++i) o[size_t(i)] = kv[size_t(i)].second;
+    return o;
+}
 
 }  // namespace
 
@@ -416,13 +543,7 @@ knn_status knn_mlp_loss_grad(knn_mlp *m, const float *x, const float *t, int64_t
     set_error("");
     if (!m || !x || !t || n <= 0) return fail(KNN_E_INVALID_ARG, "knn_mlp_loss_grad: bad argument");
     hipStream_t s = (hipStream_t)stream;
-    const int64_t nblk = (n + kGradBlock - 1) / kGradBlock;
-    KNN_TRY(ensure_grad_scratch(m, nblk));
-    k_mlp_grad<<<int(nblk), kGradBlock, 0, s>>>(dev_of(m), x, t, n, m->partial, m->lossbuf + 1);
-    k_mlp_reduce<<<int((m->P + 255) / 256), 256, 0, s>>>(m->partial, int(nblk), int(m->P), m->g,
-                                                         m->lossbuf + 1, m->lossbuf,
-                                                         1.0f / float(n));
-    KNN_HIP(hipGetLastError());
+    KNN_TRY(launch_loss_grad(m, x, t, n, s));
     if (loss_host) KNN_HIP(hipMemcpyAsync(loss_host, m->lossbuf, 4, hipMemcpyDeviceToHost, s));
     KNN_HIP(hipStreamSynchronize(s));
     return KNN_OK;
@@ -435,12 +556,7 @@ knn_status knn_mlp_adam_step(knn_mlp *m, float lr, float beta1, float beta2, flo
     if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
         return fail(KNN_E_INVALID_ARG, "knn_mlp_adam_step: bad hyper-parameters");
     hipStream_t s = (hipStream_t)stream;
-    m->step += 1;
-    const float c1 = float(1.0 - std::pow(double(beta1), double(m->step)));
-    const float c2 = float(1.0 - std::pow(double(beta2), double(m->step)));
-    k_mlp_adam<<<int((m->P + 255) / 256), 256, 0, s>>>(m->p, m->g, m->m, m->v, int(m->P), lr, beta1,
-                                                       beta2, eps, c1, c2);
-    KNN_HIP(hipGetLastError());
+    KNN_TRY(launch_adam(m, lr, beta1, beta2, eps, s));
     KNN_HIP(hipStreamSynchronize(s));
     return KNN_OK;
 }
@@ -546,5 +662,151 @@ knn_status knn_seed_radius(const knn_mlp *m, const float *feats, int64_t n, floa
     KNN_HIP(hipStreamSynchronize(s));
     return KNN_OK;
 }
+
+knn_status knn_seed_train(const float *feats, const float *kth, int64_t n, int32_t n_in,
+                          const knn_train_opts *opts, knn_mlp **out, float *log_margin_out,
+                          float *loss_out, void *stream) {
+    set_error("");
+    if (!feats || !kth || !opts || !out || !log_margin_out)
+        return fail(KNN_E_INVALID_ARG, "knn_seed_train: NULL argument");
+    *out = nullptr;
+    if (n < 2 || n > INT32_MAX) return fail(KNN_E_INVALID_ARG, "knn_seed_train: need 2 <= n < 2^31");
+    if (n_in < 1 || n_in > kMaxIn) return fail(KNN_E_INVALID_ARG, "knn_seed_train: need 1 <= n_in <= 72");
+    const knn_train_opts o = *opts;
+    if (o.epochs < 1 || o.batch < 1 || !(o.lr > 0.f) || !std::isfinite(o.lr) || !(o.val_frac > 0.f) ||
+        !(o.val_frac < 1.f) || !(o.target_fallback >= 0.f) || !(o.target_fallback < 1.f))
+        return fail(KNN_E_INVALID_ARG, "knn_seed_train: option outside its domain");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n_val = std::max<int64_t>(1, int64_t(std::floor(double(n) * double(o.val_frac))));
+    const int64_t n_tr = n - n_val;
+    const int64_t bmax = std::min<int64_t>(o.batch, n_tr);
+
+    CallBufs B{s, {}};
+    float *ylog, *xtr, *ytr, *ttr, *xva, *yva, *xb, *tb, *pred, *hist;
+    int32_t *idx, *ord;
+    double *st;
+    int *bad;
+    const int64_t steps = int64_t(o.epochs) * ((n_tr + bmax - 1) / bmax);
+    KNN_HIP(B.get(&ylog, size_t(n)));
+    KNN_HIP(B.get(&xtr, size_t(n_tr) * n_in));
+    KNN_HIP(B.get(&ytr, size_t(n_tr)));
+    KNN_HIP(B.get(&ttr, size_t(n_tr)));
+    KNN_HIP(B.get(&xva, size_t(n_val) * n_in));
+    KNN_HIP(B.get(&yva, size_t(n_val)));
+    KNN_HIP(B.get(&xb, size_t(bmax) * n_in));
+    KNN_HIP(B.get(&tb, size_t(bmax)));
+    KNN_HIP(B.get(&pred, size_t(n_val)));
+    KNN_HIP(B.get(&hist, size_t(steps)));
+    KNN_HIP(B.get(&idx, size_t(n)));
+    KNN_HIP(B.get(&ord, size_t(n_tr)));
+    KNN_HIP(B.get(&st, size_t(2 * (n_in + 1))));
+    KNN_HIP(B.get(&bad, size_t(1)));
+    const int T = 256;
+    auto blocks = [&](int64_t m) { return int((m + T - 1) / T); };
+
+    // targets, checked
+    KNN_HIP(zero_words(bad, 1, s));
+    k_train_log_targets<<<blocks(n), T, 0, s>>>(kth, n, ylog, bad);
+    KNN_HIP(hipGetLastError());
+    int bad_h = 0;
+    KNN_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipStreamSynchronize(s));
+    if (bad_h) return fail(KNN_E_INVALID_ARG, "knn_seed_train: a target is negative or not finite");
+
+    // 1. split (stream 1)
+    const std::vector<int32_t> split = key_order(splitmix_value(o.seed, 1), n);
+    KNN_HIP(hipMemcpyAsync(idx, split.data(), size_t(n) * 4, hipMemcpyHostToDevice, s));
+    k_train_gather<<<blocks(n_val), T, 0, s>>>(feats, ylog, idx, n_val, n_in, xva, yva);
+    k_train_gather<<<blocks(n_tr), T, 0, s>>>(feats, ylog, idx + n_val, n_tr, n_in, xtr, ytr);
+    // 2. standardisation
+    k_train_column_stats<<<n_in, T, 0, s>>>(xtr, n_tr, n_in, st);
+    k_train_column_stats<<<1, T, 0, s>>>(ytr, n_tr, 1, st + 2 * n_in);
+    KNN_HIP(hipGetLastError());
+    std::vector<double> sth(size_t(2 * (n_in + 1)));
+    KNN_HIP(hipMemcpyAsync(sth.data(), st, sth.size() * 8, hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipStreamSynchronize(s));
+    std::vector<float> mu(static_cast<size_t>(n_in)), isd(static_cast<size_t>(n_in));
+    for (int j = 0; j < n_in; ++j) {
+        const double sd = sth[2 * j + 1] < 1e-12 ? 1.0 : sth[2 * j + 1];
+        mu[j] = float(sth[2 * j]);
+        isd[j] = float(1.0 / sd);
+    }
+    const double y_mu = sth[2 * n_in], y_sd = std::max(sth[2 * n_in + 1], 1e-12);
+    k_train_standardise<<<blocks(n_tr), T, 0, s>>>(ytr, n_tr, y_mu, y_sd, ttr);
+    KNN_HIP(hipGetLastError());
+
+    // 3. network and initial weights (stream 0)
+    knn_mlp *m = nullptr;
+    KNN_TRY(knn_mlp_create(n_in, kH, &m));
+    std::unique_ptr<knn_mlp, void (*)(knn_mlp *)> guard(m, knn_mlp_free);
+    {
+        std::vector<float> p(size_t(m->P), 0.f);
+        const uint64_t s0 = splitmix_value(o.seed, 0);
+        uint64_t c = 0;
+        size_t at = 0;
+        const int shapes[3][2] = {{kH, n_in}, {kH, kH}, {1, kH}};
+        for (const auto &sh : shapes) {
+            const double a = std::sqrt(6.0 / double(sh[1]));
+            for (int64_t w = 0; w < int64_t(sh[0]) * sh[1]; ++w) {
+                const double u = double(splitmix_value(s0, c++) >> 11) * 0x1p-53;
+                p[at++] = float(-a + 2.0 * a * u);
+            }
+            at += size_t(sh[0]);  // biases stay 0
+        }
+        KNN_TRY(knn_mlp_set_params(m, p.data(), m->P));
+        KNN_TRY(knn_mlp_set_norm(m, mu.data(), isd.data(), float(y_mu), float(y_sd)));
+    }
+
+    // 4. epochs (stream 2 + e)
+    int64_t step = 0;
+    std::vector<int64_t> per_epoch(static_cast<size_t>(o.epochs));
+    for (int e = 0; e < o.epochs; ++e) {
+        const std::vector<int32_t> order = key_order(splitmix_value(o.seed, 2 + uint64_t(e)), n_tr);
+        KNN_HIP(hipMemcpyAsync(ord, order.data(), size_t(n_tr) * 4, hipMemcpyHostToDevice, s));
+        int64_t nb = 0;
+        for (int64_t b0 = 0; b0 < n_tr; b0 += bmax, ++nb, ++step) {
+            const int64_t bn = std::min(bmax, n_tr - b0);
+            k_train_gather<<<blocks(bn), T, 0, s>>>(xtr, ttr, ord + b0, bn, n_in, xb, tb);
+            KNN_HIP(hipGetLastError());
+            KNN_TRY(launch_loss_grad(m, xb, tb, bn, s));
+            KNN_HIP(hipMemcpyAsync(hist + step, m->lossbuf, sizeof(float), hipMemcpyDeviceToDevice, s));
+            KNN_TRY(launch_adam(m, o.lr, 0.9f, 0.999f, 1e-8f, s));
+        }
+        per_epoch[size_t(e)] = nb;
+        // the host copy of this epoch's order must outlive its upload
+        KNN_HIP(hipStreamSynchronize(s));
+    }
+
+    // 5. calibration on the held-out rows
+    const size_t lds = size_t(m->P) * sizeof(float);
+    k_mlp_forward<<<blocks(n_val), T, lds, s>>>(dev_of(m), xva, n_val, pred);
+    KNN_HIP(hipGetLastError());
+    std::vector<float> ph(static_cast<size_t>(n_val)), yh(static_cast<size_t>(n_val)),
+        hh(static_cast<size_t>(steps));
+    KNN_HIP(hipMemcpyAsync(ph.data(), pred, size_t(n_val) * 4, hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipMemcpyAsync(yh.data(), yva, size_t(n_val) * 4, hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipMemcpyAsync(hh.data(), hist, size_t(steps) * 4, hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipStreamSynchronize(s));
+    std::vector<double> r(static_cast<size_t>(n_val));
+    for (int64_t i = 0; i < n_val; ++i) r[size_t(i)] = double(yh[size_t(i)]) - (double(ph[size_t(i)]) * y_sd + y_mu);
+    std::sort(r.begin(), r.end());
+    const double h = double(n_val - 1) * (1.0 - double(o.target_fallback));
+    const int64_t lo = std::min<int64_t>(int64_t(std::floor(h)), n_val - 1);
+    const int64_t hi = std::min<int64_t>(lo + 1, n_val - 1);
+    const double margin = r[size_t(lo)] + (h - double(lo)) * (r[size_t(hi)] - r[size_t(lo)]);
+    if (!std::isfinite(margin)) return fail(KNN_E_DEVICE, "knn_seed_train: non-finite margin (training diverged)");
+    if (loss_out) {
+        int64_t at = 0;
+        for (int e = 0; e < o.epochs; ++e) {
+            double acc = 0.0;
+            for (int64_t b = 0; b < per_epoch[size_t(e)]; ++b) acc += double(hh[size_t(at++)]);
+            loss_out[e] = float(acc / double(per_epoch[size_t(e)]));
+        }
+    }
+    *log_margin_out = float(margin);
+    *out = guard.release();
+    return KNN_OK;
+}
+
 
 }  // extern "C"

@@ -103,6 +103,8 @@ _SIGS = {
     "knn_mlp_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_P)]),
     "knn_seed_features": (ctypes.c_int, [_P, _P, _P, _P]),
     "knn_seed_radius": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_float, _P, _P]),
+    "knn_seed_train": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, _P,
+                                      ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_float), _P, _P]),
     "knn_search_furthest": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(knn_opts), _P,
                                            _P, _P]),
     "knn_range_count": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double,
@@ -581,6 +583,36 @@ def knn_seed_radius(mlp: Mlp, feats, log_margin: float = 0.0, stream=None):
                                   float(log_margin), ctypes.c_void_p(r.data_ptr()),
                                   _stream(stream)))
     return r
+
+
+class knn_train_opts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("val_frac", ctypes.c_float), ("target_fallback", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+def knn_seed_train(feats, kth, epochs: int = 30, batch: int = 4096, lr: float = 3e-3,
+                   val_frac: float = 0.1, target_fallback: float = 0.05, seed: int = 0,
+                   stream=None):
+    """Train a seed network on the GPU (knn_seed_train in include/knn.h).
+    feats: contiguous CUDA float32 (n, n_in); kth: contiguous CUDA float32
+    (n,) per-leaf largest k-th distances.  Returns (Mlp, log_margin, list of
+    per-epoch mean losses)."""
+    torch = _torch()
+    if feats.dim() != 2 or kth.dim() != 1 or kth.shape[0] != feats.shape[0]:
+        raise ValueError("need feats (n, n_in) and kth (n,)")
+    for t, nm in ((feats, "feats"), (kth, "kth")):
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError(f"{nm} must be a contiguous CUDA float32 tensor")
+    o = knn_train_opts(int(epochs), int(batch), float(lr), float(val_frac),
+                       float(target_fallback), int(seed) & 0xFFFFFFFFFFFFFFFF)
+    h = ctypes.c_void_p()
+    margin = ctypes.c_float()
+    losses = np.zeros(int(epochs), np.float32) if epochs > 0 else np.zeros(1, np.float32)
+    _check(load().knn_seed_train(ctypes.c_void_p(feats.data_ptr()), ctypes.c_void_p(kth.data_ptr()),
+                                 feats.shape[0], feats.shape[1], ctypes.byref(o), ctypes.byref(h),
+                                 ctypes.byref(margin), losses.ctypes.data, _stream(stream)))
+    return Mlp(handle=h), margin.value, [float(v) for v in losses]
 
 
 # ---------------------------------------------------------------------------

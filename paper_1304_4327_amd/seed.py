@@ -1,16 +1,14 @@
 """Training and use of the learned seed radius (host orchestration).
 
-The network, its gradients and the Adam updates run in the library's kernels
-(``knn_mlp_*``); the search consumes the predicted radii through
-``knn_opts.seed_radius``.  This module only moves data: it runs plain
-searches to collect per-query-leaf targets, standardises inputs and targets
-(means and deviations computed on the host), feeds mini-batches, and
-calibrates an additive log-margin on a held-out split.
+Training runs in the library (``knn_seed_train``: split, standardisation,
+mini-batch gradients and Adam steps, margin calibration); the search consumes
+the predicted radii through ``knn_opts.seed_radius``.  This module only runs
+the plain searches that produce the training rows and stacks them.
 
-Target of a query leaf: log of the largest k-th neighbour distance among its
-points (the smallest seed for which the leaf needs no fallback).  Features:
-leaf box centre, lambda, point count, log density of the reference leaf
-reached from the centre (``knn_seed_features``).
+Target of a query leaf: the largest k-th neighbour distance among its points
+(the smallest seed for which the leaf needs no fallback); the network learns
+its log.  Features: leaf box centre, lambda, point count, log density of the
+reference leaf reached from the centre (``knn_seed_features``).
 """
 from __future__ import annotations
 
@@ -30,7 +28,8 @@ class SeedModel:
 
 
 def leaf_data(ref_pts, q_pts, k: int, leaf: int, precision: str = "fp32"):
-    """Plain search on (ref, q) -> (features tensor, log-target tensor, stats)."""
+    """Plain search on (ref, q) -> (features, per-leaf k-th distances, stats),
+    both CUDA float32 tensors."""
     import torch
     R = torch.from_numpy(np.ascontiguousarray(ref_pts)).cuda()
     rt = K.knn_build_tree(R, leaf)
@@ -48,51 +47,19 @@ def leaf_data(ref_pts, q_pts, k: int, leaf: int, precision: str = "fp32"):
     if qt is not None:
         qt.close()
     rt.close()
-    y = torch.from_numpy(np.log(np.maximum(kth.cpu().numpy().astype(np.float64), 1e-30))
-                         .astype(np.float32)).cuda()
-    return feats, y, st
+    return feats, kth, st
 
 
-def fit(feats_list, y_list, epochs: int = 30, batch: int = 4096, lr: float = 3e-3,
+def fit(feats_list, kth_list, epochs: int = 30, batch: int = 4096, lr: float = 3e-3,
         seed: int = 0, val_frac: float = 0.1, target_fallback: float = 0.05) -> SeedModel:
-    """Train the seed network on stacked (features, log-target) pairs."""
+    """Train the seed network on stacked (features, k-th distance) rows."""
     import torch
     X = torch.cat(list(feats_list)).contiguous()
-    Y = torch.cat(list(y_list)).contiguous()
-    n = X.shape[0]
-    order = np.random.default_rng(seed).permutation(n)
-    n_val = max(1, int(n * val_frac))
-    val_idx = torch.from_numpy(order[:n_val]).cuda()
-    tr_idx = torch.from_numpy(order[n_val:]).cuda()
-    Xtr, Ytr = X[tr_idx].contiguous(), Y[tr_idx]
-    Xva, Yva = X[val_idx].contiguous(), Y[val_idx]
-    xh = Xtr.double().cpu().numpy()
-    yh = Ytr.double().cpu().numpy()
-    mu = xh.mean(axis=0)
-    sd = xh.std(axis=0)
-    sd[sd < 1e-12] = 1.0
-    y_mu, y_sd = float(yh.mean()), float(max(yh.std(), 1e-12))
-    Ttr = torch.from_numpy(((yh - y_mu) / y_sd).astype(np.float32)).cuda()
-
-    n_in = X.shape[1]
-    mlp = K.Mlp(n_in)
-    mlp.set_params(datagen.mlp_init(n_in, 64, seed))
-    mlp.set_norm(mu.astype(np.float32), (1.0 / sd).astype(np.float32), y_mu, y_sd)
-    history = []
-    for ep in range(epochs):
-        losses = []
-        for bi in datagen.batches(Xtr.shape[0], batch, seed * 100003 + ep):
-            idx = torch.from_numpy(bi).cuda()
-            xb = Xtr[idx].contiguous()
-            tb = Ttr[idx].contiguous()
-            losses.append(mlp.loss_grad(xb, tb))
-            mlp.adam_step(lr)
-        history.append(float(np.mean(losses)))
-    # calibration: residual quantile on the held-out split
-    pred = mlp.forward(Xva).double().cpu().numpy() * y_sd + y_mu
-    resid = Yva.double().cpu().numpy() - pred
-    log_margin = float(np.quantile(resid, 1.0 - target_fallback))
-    return SeedModel(mlp, log_margin, history)
+    Y = torch.cat(list(kth_list)).contiguous()
+    mlp, margin, history = K.knn_seed_train(X, Y, epochs=epochs, batch=batch, lr=lr,
+                                            val_frac=val_frac, target_fallback=target_fallback,
+                                            seed=seed)
+    return SeedModel(mlp, margin, history)
 
 
 def radii(model: SeedModel, feats):
@@ -104,10 +71,10 @@ def train_for_workload(name: str, train_seeds, scale: float = 1.0, precision: st
                        **kw) -> SeedModel:
     """Targets come from plain (exact) searches on the training seeds; the
     precision only picks which exact path produces them."""
-    feats, ys = [], []
+    feats, kths = [], []
     for s in train_seeds:
         ref, q, k, leaf = datagen.make(name, seed=s, scale=scale)
-        f, y, _ = leaf_data(ref, q, k, leaf, precision=precision)
+        f, kth, _ = leaf_data(ref, q, k, leaf, precision=precision)
         feats.append(f)
-        ys.append(y)
-    return fit(feats, ys, **kw)
+        kths.append(kth)
+    return fit(feats, kths, **kw)

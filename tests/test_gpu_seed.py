@@ -176,3 +176,65 @@ def test_trained_seed_prunes_more_and_stays_exact():
     # the seeded pass itself prunes more than the plain search; the total
     # (with the fallback pass) is reported by the benchmark
     assert st["pairs"] - st["fallback_pairs"] < plain["pairs"]
+
+
+def _train_data(n, n_in, seed):
+    """Feature rows of seed-feature scale (centres, lambda, counts, log
+    densities) and k-th distances log-linear in them, with noise."""
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(n, n_in)) * rng.uniform(0.1, 30.0, n_in) + rng.uniform(-50, 50, n_in)
+    w = rng.normal(size=n_in) / (1.0 + np.abs(x).mean(axis=0))
+    kth = np.exp(x @ w + 0.1 * rng.normal(size=n))
+    return x.astype(np.float32), kth.astype(np.float32)
+
+
+@pytest.mark.parametrize("n,n_in,epochs,batch", [(300, 6, 2, 64), (1000, 11, 1, 1000),
+                                                 (257, 67, 3, 50), (4096, 11, 4, 512)])
+def test_seed_train_follows_the_fp64_procedure(n, n_in, epochs, batch):
+    """knn_seed_train against the FP64 training procedure with the same
+    random streams: per-epoch losses, predictions on every row (these carry
+    the standardisation), and the calibrated margin.  The FP32 and FP64 runs
+    drift apart by rounding only; the bounds are a few times the drift the
+    FP32 gradient (about 1e-6 relative) can build up over these step
+    counts."""
+    torch = _torch()
+    from paper_1304_4327_amd import knn
+    x, kth = _train_data(n, n_in, n + n_in)
+    lr, vf, tf, seed = 1e-3, 0.2, 0.1, 17 + n
+    net, margin, losses = knn.knn_seed_train(torch.from_numpy(x).cuda(), torch.from_numpy(kth).cuda(),
+                                            epochs=epochs, batch=batch, lr=lr, val_frac=vf,
+                                            target_fallback=tf, seed=seed)
+    p, mu, isd, y_mu, y_sd, om, hist = omlp.train(x, kth, epochs, batch, lr, vf, tf, seed)
+    np.testing.assert_allclose(losses, hist, rtol=2e-3)
+    gy = net.forward(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
+    oy = omlp.forward(p, x, mu, isd, n_in, 64)
+    assert np.max(np.abs(gy - oy)) < 2e-3 * max(1.0, np.max(np.abs(oy)))
+    assert abs(margin - om) < 5e-3 * y_sd
+    gp = net.get_params().astype(np.float64)
+    assert np.mean(np.abs(gp - p) < 1e-4) > 0.99
+
+
+def test_seed_train_is_deterministic_and_checks_targets():
+    torch = _torch()
+    from paper_1304_4327_amd import knn
+    x, kth = _train_data(500, 11, 3)
+    X, K_ = torch.from_numpy(x).cuda(), torch.from_numpy(kth).cuda()
+    a, ma, la = knn.knn_seed_train(X, K_, epochs=2, batch=100, seed=5)
+    b, mb, lb = knn.knn_seed_train(X, K_, epochs=2, batch=100, seed=5)
+    assert np.array_equal(a.get_params(), b.get_params()) and ma == mb and la == lb
+    c, *_ = knn.knn_seed_train(X, K_, epochs=2, batch=100, seed=6)
+    assert not np.array_equal(a.get_params(), c.get_params())
+    for badv in (-1.0, float("nan"), float("inf")):
+        kb = kth.copy()
+        kb[77] = badv
+        with pytest.raises(knn.KnnError) as e:
+            knn.knn_seed_train(X, torch.from_numpy(kb).cuda(), epochs=1)
+        assert e.value.status == knn.KNN_E_INVALID_ARG
+    with pytest.raises(knn.KnnError):
+        knn.knn_seed_train(X[:1].contiguous(), K_[:1].contiguous(), epochs=1)
+    with pytest.raises(knn.KnnError):
+        knn.knn_seed_train(X, K_, epochs=1, val_frac=1.0)
+    # a zero distance (duplicate points) is a valid target
+    kz = kth.copy()
+    kz[:5] = 0.0
+    knn.knn_seed_train(X, torch.from_numpy(kz).cuda(), epochs=1)
