@@ -229,6 +229,7 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     a.rperm = ref->perm;
     a.rrange = ref->range;
     a.rbox = ref->box;
+    a.rlam = ref->lam;
     a.rlpts = ref->lpts;
     a.r_leaf_slots = ref->leaf_slots;
     a.r_first_leaf = int(ref->first_leaf);

@@ -147,6 +147,12 @@ struct OpMax {
 struct OpMin {
     __device__ float operator()(float a, float b) const { return fminf(a, b); }
 };
+// bitwise OR of the two values' bit patterns (a 32-bit mask carried in a float)
+struct OpOrBits {
+    __device__ float operator()(float a, float b) const {
+        return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, a) | __builtin_bit_cast(uint32_t, b));
+    }
+};
 
 
 // tree construction (tree_build.hip)

@@ -21,6 +21,7 @@ struct SearchArgs {
     const int32_t *rperm;
     const int2 *rrange;
     const float *rbox;
+    const float *rlam;
     const float *rlpts;  // leaf-blocked points (r_leaf_slots per leaf)
     int r_leaf_slots;
     int r_first_leaf;

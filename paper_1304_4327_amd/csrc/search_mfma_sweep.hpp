@@ -1,38 +1,55 @@
-// BF16 matrix-core kernel for the high-dimensional regime: the same Score,
+// BF16 matrix-core kernel for the high-dimensional regime: the same
 // BaseCase tiles, bounds and exactness argument as the per-leaf MFMA kernel
-// (k_search_mfma), with the reference tree visited as a sweep over its
-// leaves instead of a depth-first walk.
+// (k_search_mfma), with the reference tree visited as a sweep over blocks of
+// its leaves instead of a depth-first walk.
 //
 // Why a sweep.  With d = 64 and tens of thousands of reference leaves, the
-// nearest-first walk enters almost every leaf anyway, and its cost becomes
-// the chain of dependent box loads on the way down and back up.  A sweep
-// scores every reference leaf against the query leaves' current bounds --
-// still a pruning dual-tree traversal (every pair (N_q, N_r) is scored at
-// most once and pruned when d_min exceeds the bound), only in another
-// order -- and lets the next leaf's data load while the current one is
-// processed.  The order starts at the leaf that the query node's box
-// centre falls in and moves outward in tree order, which keeps near leaves
-// first.
+// nearest-first walk enters most leaves anyway, and its cost becomes the
+// chain of dependent box loads on the way down and back up.  The sweep
+// scores every reference leaf against the query points' current bounds --
+// still a pruning dual-tree traversal (every pair (N_q, N_r) is scored once
+// and pruned when d_min exceeds the bound), only in another order -- and
+// loads the next kept leaf while the current one is processed.
+//
+// Score.  The sweep takes blocks of 32 consecutive reference leaves (the
+// leaves of one subtree), outward in tree order from the block of the leaf
+// the query node's box centre falls in (neighbours in tree order are
+// neighbours in space, so near blocks come first).  Each (query point p,
+// reference leaf N_r) pair of a block is scored as the singleton query node
+// {p} against N_r, with d_min({p}, N_r) >= ||p - C_r|| - lambda(N_r): every
+// point of N_r lies within lambda of its box centre C_r.  The pair is pruned
+// when that exceeds p's bound min(D_p[k], B(N_q)).  The 32 x 32 values
+// ||p - C_r||^2 of a block are one BF16 MFMA tile of the queries against the
+// leaf centres, with the proven margin of the distance tiles; the test takes
+// the margin's low end, so it keeps every pair the exact test keeps.  In high
+// dimension this prunes far more than the box-to-box distance: a 32-point
+// kd-tree leaf is split on at most depth-many dimensions, and its box spans
+// the leaf's whole spread in all the others.
 //
 // Mapping: one workgroup of four wavefronts owns four sibling query leaves
-// (<= 32 points each, one leaf per wave).  A reference leaf kept by any of
-// the four is staged once into LDS by all 256 threads -- centred on the
-// centre c of the query leaves' union box and rounded to BF16, its FP32 rows
-// beside it for the exact re-score, and its centred row norms -- and every
-// wave whose own leaf keeps it multiplies it against its 32 queries with
-// v_mfma_f32_32x32x16_bf16 (layout, filter margin and FP64 re-score as in
-// k_search_mfma).  The staged tiles are double-buffered: one workgroup
-// barrier per kept leaf publishes the waves' bounds and the last staged
-// tile; after it each wave multiplies that tile, then stages the next kept
-// leaf into the other buffer.  The query node above the four leaves adds the
-// B(Par) term min over all its queries of D_p[k] + 2 lambda(node).
+// (<= 32 points each, one leaf per wave).  Per block, all 256 threads stage
+// the 32 leaf centres (centred on the centre c of the query leaves' union
+// box, rounded to BF16) into LDS; each wave scores them against its 32
+// queries and ORs the kept leaves into its own 32-bit mask; the union of the
+// four masks is the list of leaves the workgroup stages.  A kept leaf is
+// staged once into LDS by all 256 threads -- centred and rounded to BF16, its
+// FP32 rows beside it for the exact re-score, and its centred row norms --
+// and every wave whose own mask holds it multiplies it against its 32
+// queries with v_mfma_f32_32x32x16_bf16 (layout, filter margin and FP64
+// re-score as in k_search_mfma).  The staged tiles are double-buffered: one
+// workgroup barrier per kept leaf publishes the tile staged last; after it
+// each wave multiplies that tile, then stages the next kept leaf into the
+// other buffer.  The waves exchange their bounds once per block: the query
+// node above the four leaves adds the B(Par) term, min over all its queries
+// of D_p[k] + 2 lambda(node).
 #pragma once
 
 #include "search_mfma.hpp"
 
 namespace knnx {
 
-constexpr int kWgLeaves = 4;  // query leaves (one per wave) per workgroup
+constexpr int kWgLeaves = 4;   // query leaves (one per wave) per workgroup
+constexpr int kSweepBlock = 32;  // reference leaves scored together
 
 // LDS layout of one workgroup
 template <int DP, int K>
@@ -43,22 +60,31 @@ struct SweepLds {
     static constexpr size_t q_rows = size_t(kWgLeaves) * 32 * DP * 4;
     static constexpr size_t merge = size_t(64) * K * 8;  // one wave's half-lists
     static constexpr size_t region = q_rows > merge ? q_rows : merge;
-    // two buffers of each per-tile array
+    // two buffers of each per-tile array, one block of leaf centres
     static constexpr size_t off_tile_f = 0;
     static constexpr size_t off_tile_bf = off_tile_f + 2 * tile_f;
-    static constexpr size_t off_region = off_tile_bf + 2 * tile_bf;
+    static constexpr size_t off_ctr_bf = off_tile_bf + 2 * tile_bf;
+    static constexpr size_t off_region = off_ctr_bf + tile_bf;
     static constexpr size_t off_cen = off_region + region;
     static constexpr size_t off_rn = off_cen + size_t(DP) * 4;
-    // misc: bounds exchange slots [2 parities][2][kWgLeaves], then the
-    // largest row norm per wave of each tile buffer [2][kWgLeaves]
-    static constexpr size_t off_misc = off_rn + 2 * 32 * 4;
+    static constexpr size_t off_ctr_n = off_rn + 2 * 32 * 4;    // centre norms
+    static constexpr size_t off_ctr_lam = off_ctr_n + 32 * 4;   // leaf lambdas
+    // misc words (kMisc*)
+    static constexpr size_t off_misc = off_ctr_lam + 32 * 4;
     static constexpr size_t bytes = off_misc + 32 * 4;
 };
+// misc words: each wave's bound and smallest k-th distance, the largest row
+// norm of each wave's staged rows per tile buffer, the same for the block of
+// centres, and each wave's block mask
+constexpr int kMiscBound = 0;     // [2][kWgLeaves]
+constexpr int kMiscTileMax = 8;   // [2][kWgLeaves]
+constexpr int kMiscCtrMax = 16;   // [kWgLeaves]
+constexpr int kMiscMask = 20;     // [kWgLeaves]
 
 // Two workgroups per CU (two waves per SIMD) where the lists allow it: each
 // tile's latency chain (staging barrier, dependent MFMAs, LDS reads) is then
-// covered by the other workgroup.  For K <= 50 this fits 256 registers with a
-// few spills off the tile loop; larger lists keep one workgroup.
+// covered by the other workgroup.  For K <= 50 this fits 256 registers;
+// larger lists keep one workgroup.
 template <int DP, int K>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 50 ? 2 : 1))) void
 k_search_mfma_sweep(const SearchArgs a) {
@@ -66,15 +92,20 @@ k_search_mfma_sweep(const SearchArgs a) {
     using L = SweepLds<DP, K>;
     constexpr int S = DP / 16;  // k-steps of 16 dimensions
     constexpr int E = DP / 8;   // staged floats per thread (32 rows x DP / 256)
+    constexpr int NB = kSweepBlock;
     constexpr float kInf = __builtin_inff();
     constexpr float kSlack = 1.0f + 0x1p-16f;
     __shared__ __align__(16) char smem[L::bytes];
     float *s_tf = reinterpret_cast<float *>(smem + L::off_tile_f);
     __bf16 *s_tb = reinterpret_cast<__bf16 *>(smem + L::off_tile_bf);
+    __bf16 *s_cb = reinterpret_cast<__bf16 *>(smem + L::off_ctr_bf);
     float *s_q = reinterpret_cast<float *>(smem + L::off_region);
     float *s_cen = reinterpret_cast<float *>(smem + L::off_cen);
     float *s_rn = reinterpret_cast<float *>(smem + L::off_rn);
+    float *s_cn = reinterpret_cast<float *>(smem + L::off_ctr_n);
+    float *s_cl = reinterpret_cast<float *>(smem + L::off_ctr_lam);
     float *s_misc = reinterpret_cast<float *>(smem + L::off_misc);
+    uint32_t *s_mask = reinterpret_cast<uint32_t *>(s_misc + kMiscMask);
     // workgroup barrier that waits for this wave's LDS traffic only: the
     // next leaf's global loads stay in flight across it
     auto lds_barrier = [] { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); };
@@ -119,28 +150,6 @@ k_search_mfma_sweep(const SearchArgs a) {
         }
     }
     if (w == 0 && lane < DP) s_cen[lane] = 0.5f * (ulo + uhi);
-    // each leaf's own box for Score: 16 lanes per leaf, lane l holds
-    // dimensions (l % 16) * DPL .. + DPL - 1 of leaf l / 16, so one 16-lane
-    // reduction (DPP row operations only) scores a node for all four leaves
-    // (an idle leaf's box is empty: lo = +inf, hi = -inf, so its d_min is
-    // +inf)
-    static_assert(kWgLeaves * 16 == 64, "Score layout: 16 lanes per query leaf");
-    constexpr int DPL = DP / 16;
-    const int sg = lane >> 4, sd = (lane & 15) * DPL;
-    float plo[DPL], phi[DPL];
-#pragma unroll
-    for (int e = 0; e < DPL; ++e) {
-        plo[e] = kInf;
-        phi[e] = -kInf;
-    }
-    if (leaf_on(leaf0 + sg)) {
-        const float *qb = a.qbox + int64_t(a.q_first_leaf + leaf0 + sg) * 2 * DP;
-#pragma unroll
-        for (int e = 0; e < DPL; ++e) {
-            plo[e] = qb[sd + e];
-            phi[e] = qb[DP + sd + e];
-        }
-    }
     // this wave's query rows (FP32) for the exact re-score; zero for idle lanes
     float *my_q = s_q + (w * 32 + j) * DP;
 #pragma unroll
@@ -189,55 +198,10 @@ k_search_mfma_sweep(const SearchArgs a) {
     }
     float bound2 = (a.bound == KNN_BOUND_NONE) ? kInf : seed2;  // this wave's B^2
     float lo_k = kInf;      // min over the wave's queries of D_p[k]^2
-    float bnd[kWgLeaves];   // every leaf's pruning bound (squared, times the prune
-                            // slack), the same in all waves
-#pragma unroll
-    for (int g = 0; g < kWgLeaves; ++g) bnd[g] = kInf;
     float pair_kth = kInf;  // min of the two half-list k-ths of this query
     uint32_t n_score = 0, n_tiles = 0, n_ins = 0, n_pass = 0;
     uint64_t n_pairs = 0;
 
-    // publish the waves' bounds, then every wave derives the same
-    // workgroup bound.  The barrier also makes the last staged tile visible.
-    // The slots alternate between two parities: a wave may publish the next
-    // exchange's values before a slower wave has read this one's.
-    int xp = 0;
-    auto exchange_bounds = [&]() {
-        float *sb = s_misc + xp * 2 * kWgLeaves;
-        if (lane == 0) {
-            sb[w] = has_leaf ? bound2 : -kInf;
-            sb[kWgLeaves + w] = has_leaf ? lo_k : kInf;
-        }
-        lds_barrier();
-        xp ^= 1;
-        float lo_all = kInf;
-#pragma unroll
-        for (int g = 0; g < kWgLeaves; ++g) lo_all = fminf(lo_all, sb[kWgLeaves + g]);
-        float bp = kInf;
-        if (a.bound == KNN_BOUND_B && lo_all < kInf && lam2_anc < kInf) {
-            // hardware square root (1 ulp): far inside the prune slack
-            const float t = __builtin_amdgcn_sqrtf(lo_all) + lam2_anc;
-            bp = t * t;
-        }
-        bound2 = fminf(bound2, bp);
-#pragma unroll
-        for (int g = 0; g < kWgLeaves; ++g) bnd[g] = uniform_f(fminf(sb[g], bp) * kSlack);
-    };
-
-    // d_min^2 between each leaf's box and a reference node's box; a node is
-    // kept when any leaf would keep it (its d_min within that leaf's bound)
-    auto score_node = [&](const float (&lo)[DPL], const float (&hi)[DPL], float (&dm)[kWgLeaves]) {
-        float sum = 0.f;
-#pragma unroll
-        for (int e = 0; e < DPL; ++e) {
-            const float gap = fmaxf(fmaxf(lo[e] - phi[e], plo[e] - hi[e]), 0.0f);
-            sum = fmaf(gap, gap, sum);
-        }
-        sum = reduce16(sum, OpAdd());
-#pragma unroll
-        for (int g = 0; g < kWgLeaves; ++g)
-            dm[g] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sum), 16 * g));
-    };
     auto refresh_bound = [&]() {
         pair_kth = xor32_op(dist[K - 1], OpMin());
         if (a.bound == KNN_BOUND_NONE) return;
@@ -289,13 +253,12 @@ k_search_mfma_sweep(const SearchArgs a) {
         uint32_t rmu = 0u;
 #pragma unroll
         for (int g = 0; g < 8; ++g) rmu = max(rmu, (uint32_t)__builtin_amdgcn_readlane(rnb, 8 * g));
-        if (lane == 0) s_misc[4 * kWgLeaves + b * kWgLeaves + w] = __builtin_bit_cast(float, rmu);
+        if (lane == 0) s_misc[kMiscTileMax + b * kWgLeaves + w] = __builtin_bit_cast(float, rmu);
     };
     // one staged tile (buffer b, leaf rows base .. base + cnt) against this
-    // wave's queries; own: the d_min^2 of this wave's leaf to the leaf's box,
-    // re-checked against the bound as it stands now
-    auto compute = [&](int b, int base, int cnt, float own) __attribute__((always_inline)) {
-        if (!has_leaf || own > bound2 * kSlack) return;
+    // wave's queries; own: the leaf is in this wave's block mask
+    auto compute = [&](int b, int base, int cnt, bool own) __attribute__((always_inline)) {
+        if (!own) return;
         const __bf16 *tb = s_tb + b * 32 * L::kRowBf;
         const float *tf = s_tf + b * 32 * DP;
         const float *trn = s_rn + b * 32;
@@ -305,7 +268,7 @@ k_search_mfma_sweep(const SearchArgs a) {
         // the margin only needs an upper bound)
         float rmax = 0.f;
 #pragma unroll
-        for (int g = 0; g < kWgLeaves; ++g) rmax = fmaxf(rmax, s_misc[4 * kWgLeaves + b * kWgLeaves + g]);
+        for (int g = 0; g < kWgLeaves; ++g) rmax = fmaxf(rmax, s_misc[kMiscTileMax + b * kWgLeaves + g]);
         const float rlen = __builtin_amdgcn_sqrtf(uniform_f(rmax)) * (1.0f + 0x1p-20f);
         f32x16_t acc;
 #pragma unroll
@@ -361,13 +324,9 @@ k_search_mfma_sweep(const SearchArgs a) {
         refresh_bound();
     };
 
-    exchange_bounds();
-
-    // ---- sweep: the reference leaves in tree order, outward from the leaf
-    // the union centre falls in (neighbours in tree order are neighbours in
-    // space, so near leaves come first); each leaf is scored against every
-    // query leaf's bound and pruned or processed.  The next leaf's box, range
-    // and rows are loaded while the current one is processed. -------------
+    // ---- the sweep ---------------------------------------------------------
+    // start: the reference leaf the union centre falls in (descent by box
+    // distance of the centre to the two children)
     int start = 0;
     {
         const float cq = lane < DP ? 0.5f * (ulo + uhi) : 0.f;
@@ -385,30 +344,113 @@ k_search_mfma_sweep(const SearchArgs a) {
         start = node - a.r_first_leaf;
     }
     const int nl = a.r_first_leaf + 1;  // reference leaves
-    const int steps = 2 * max(start, nl - 1 - start) + 1;
-    auto leaf_of = [&](int st) {
-        const int off = (st + 1) >> 1;
-        return (st & 1) ? start + off : start - off;
-    };
-    auto advance = [&](int st) {
-        while (st < steps) {
-            const int l = leaf_of(st);
-            if (l >= 0 && l < nl) break;
-            ++st;
-        }
-        return st;
-    };
-    // loads of one leaf: range, this lane's box coordinates, this thread's
-    // rows (the leaf-blocked copy has r_leaf_slots <= 32 rows per leaf)
-    auto fetch = [&](int leaf, int2 &rr, float (&blo)[DPL], float (&bhi)[DPL], float (&v)[E]) {
-        const int node = a.r_first_leaf + leaf;
-        rr = a.rrange[node];
-        const float *b = a.rbox + int64_t(node) * 2 * DP;
+    const int n_blocks = (nl + NB - 1) / NB;
+    const int sblock = start / NB;
+    const int bsteps = 2 * max(sblock, n_blocks - 1 - sblock) + 1;
+
+    // stage the box centres C = (lo + hi) / 2 of block rb's leaves (row trow =
+    // leaf NB rb + trow, this thread's E columns), centred on c and rounded
+    // to BF16, with their FP32 norms and lambdas; rows past the tree and
+    // empty leaves get an infinite norm.  Also publishes this wave's bounds.
+    auto stage_centres = [&](int rb) {
+        const int leaf = rb * NB + trow;
+        const int node = a.r_first_leaf + min(leaf, nl - 1);
+        const bool vrow = leaf < nl && a.rrange[node].y > 0;
+        const float *bx = a.rbox + int64_t(node) * 2 * DP;
+        float rn = 0.f;
 #pragma unroll
-        for (int e = 0; e < DPL; ++e) {
-            blo[e] = b[sd + e];
-            bhi[e] = b[DP + sd + e];
+        for (int e = 0; e < E; e += 4) {
+            const float4 lo = *reinterpret_cast<const float4 *>(bx + tcol + e);
+            const float4 hi = *reinterpret_cast<const float4 *>(bx + DP + tcol + e);
+            const float cv[4] = {0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z),
+                                 0.5f * (lo.w + hi.w)};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float cd = vrow ? cv[u] - tc[e + u] : 0.f;
+                rn = fmaf(cd, cd, rn);
+                s_cb[trow * L::kRowBf + tcol + e + u] = (__bf16)cd;
+            }
         }
+        rn = reduce8(rn, OpAdd());
+        if ((tid & 7) == 0) {
+            s_cn[trow] = vrow ? rn : kInf;
+            s_cl[trow] = vrow ? a.rlam[node] : 0.f;
+        }
+        const int rnb = __builtin_bit_cast(int, vrow ? rn : 0.f);
+        uint32_t rmu = 0u;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) rmu = max(rmu, (uint32_t)__builtin_amdgcn_readlane(rnb, 8 * g));
+        if (lane == 0) {
+            s_misc[kMiscCtrMax + w] = __builtin_bit_cast(float, rmu);
+            s_misc[kMiscBound + w] = has_leaf ? bound2 : -kInf;
+            s_misc[kMiscBound + kWgLeaves + w] = has_leaf ? lo_k : kInf;
+        }
+    };
+    // after the barrier: every wave's bounds give the B(Par) term
+    auto take_bounds = [&]() {
+        float lo_all = kInf;
+#pragma unroll
+        for (int g = 0; g < kWgLeaves; ++g) lo_all = fminf(lo_all, s_misc[kMiscBound + kWgLeaves + g]);
+        if (a.bound == KNN_BOUND_B && lo_all < kInf && lam2_anc < kInf) {
+            // hardware square root (1 ulp): far inside the prune slack
+            const float t = __builtin_amdgcn_sqrtf(lo_all) + lam2_anc;
+            bound2 = uniform_f(fminf(bound2, t * t));
+        }
+    };
+    // Score of the staged block against this wave's queries: bit i of the
+    // result is set when some query p of the wave keeps leaf i, i.e. when
+    // the low end of ||p - C_i||^2 does not exceed (b_p + lambda_i)^2, b_p =
+    // sqrt(min(pair_kth, B^2)) rounded up (rows of invalid leaves never; with
+    // KNN_BOUND_NONE every valid row)
+    auto block_mask = [&]() -> uint32_t {
+        float cmax = 0.f;
+#pragma unroll
+        for (int g = 0; g < kWgLeaves; ++g) cmax = fmaxf(cmax, s_misc[kMiscCtrMax + g]);
+        const float clen = __builtin_amdgcn_sqrtf(uniform_f(cmax)) * (1.0f + 0x1p-20f);
+        const uint32_t vrows = uint32_t(ballot(lane < 32 && s_cn[lane & 31] < kInf));
+        f32x16_t acc;
+        float lam[16];
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+            const float4 v = *reinterpret_cast<const float4 *>(&s_cn[g4 * 8 + h * 4]);
+            const float4 l = *reinterpret_cast<const float4 *>(&s_cl[g4 * 8 + h * 4]);
+            acc[g4 * 4 + 0] = v.x;
+            acc[g4 * 4 + 1] = v.y;
+            acc[g4 * 4 + 2] = v.z;
+            acc[g4 * 4 + 3] = v.w;
+            lam[g4 * 4 + 0] = l.x;
+            lam[g4 * 4 + 1] = l.y;
+            lam[g4 * 4 + 2] = l.z;
+            lam[g4 * 4 + 3] = l.w;
+        }
+        const __bf16 *arow = s_cb + j * L::kRowBf + h * 8;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const bf16x8_t ar = *reinterpret_cast<const bf16x8_t *>(arow + s * 16);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, bq[s], acc, 0, 0, 0);
+        }
+        const float lim = fminf(pair_kth, bound2);
+        const float bp = lim < kInf ? __builtin_amdgcn_sqrtf(fmaxf(lim, 0.f)) * (1.0f + 0x1p-20f) : kInf;
+        const float low0 = qn - bf16_margin<DP>(qlen, clen);
+        uint32_t m = 0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float t = bp + lam[r];
+            const bool keep = !(acc[r] + low0 > t * t * kSlack);
+            m |= keep ? (1u << (8 * (r >> 2) + 4 * h + (r & 3))) : 0u;
+        }
+        // without pruning every leaf of the block is evaluated
+        m = !valid ? 0u : a.bound == KNN_BOUND_NONE ? 0xffffffffu : m;
+        // OR over the wave
+        float mf = __builtin_bit_cast(float, m);
+        mf = reduce64(mf, OpOrBits());
+        return uint32_t(uniform_i(__builtin_bit_cast(int, mf))) & vrows;
+    };
+
+    // loads of one kept leaf: range and this thread's rows (the leaf-blocked
+    // copy has r_leaf_slots <= 32 rows per leaf)
+    auto fetch = [&](int leaf, int2 &rr, float (&v)[E]) {
+        rr = a.rrange[a.r_first_leaf + leaf];
         // unconditional loads (a clamped row; rows past the leaf are masked
         // at staging): a load under a branch makes the compiler wait for
         // every load in flight where the paths join
@@ -420,72 +462,73 @@ k_search_mfma_sweep(const SearchArgs a) {
             v[e + 1] = x.y;
         }
     };
-    // score a fetched leaf; when any query leaf keeps it: exchange bounds
-    // (the barrier that publishes the tile staged last), stage this leaf
-    // into the other buffer, multiply the tile staged last.  Every wave
-    // takes the same decisions (bnd is the same in all of them), so the
-    // barriers match.  Safety of the two buffers: a wave stages into the
-    // buffer of the tile before last, and every wave finished that tile
-    // before it reached the barrier this wave has just passed.
+    // a kept leaf: the barrier publishes the tile staged last, then this leaf
+    // is staged into the other buffer and the tile staged last multiplied.
+    // Every wave takes the same steps (the block's union mask is the same in
+    // all of them), so the barriers match.  Safety of the two buffers: a
+    // wave stages into the buffer of the tile before last, and every wave
+    // finished that tile before it reached the barrier this wave has just
+    // passed.
     int pend_b = 1, pend_base = 0, pend_cnt = 0;  // the staged, unmultiplied tile
-    float pend_own = kInf;
-    bool pending = false;
-    auto visit = [&](int2 rr, const float (&blo)[DPL], const float (&bhi)[DPL], const float (&v)[E]) {
-        float dm[kWgLeaves];
-        score_node(blo, bhi, dm);
-        ++n_score;
-        // wave-uniform tests: ballots of uniform compares go straight into
-        // a scalar mask
-        uint64_t keep = 0;
-        float own = dm[0];
-#pragma unroll
-        for (int g = 0; g < kWgLeaves; ++g) {
-            keep |= ballot(!(dm[g] > bnd[g]));
-            own = (w == g) ? dm[g] : own;
-        }
-        if (keep) {
-            exchange_bounds();
-            const int b = pend_b ^ 1;
-            const int cnt = uniform_i(rr.y);
-            stage(b, cnt, v);
-            if (pending) compute(pend_b, pend_base, pend_cnt, pend_own);
-            pending = true;
-            pend_b = b;
-            pend_base = uniform_i(rr.x);
-            pend_cnt = cnt;
-            pend_own = own;
-        }
+    bool pend_own = false, pending = false;
+    auto visit = [&](int2 rr, const float (&v)[E], bool own) {
+        lds_barrier();
+        const int b = pend_b ^ 1;
+        const int cnt = uniform_i(rr.y);
+        stage(b, cnt, v);
+        if (pending) compute(pend_b, pend_base, pend_cnt, pend_own);
+        pending = true;
+        pend_b = b;
+        pend_base = uniform_i(rr.x);
+        pend_cnt = cnt;
+        pend_own = own;
     };
-    // two register sets used in turn: a leaf's loads land in the set that
-    // the next visit reads, so they stay in flight while the current leaf
-    // is processed (no register copy forces an early wait)
-    {
+
+    for (int st = 0; st < bsteps; ++st) {
+        const int off = (st + 1) >> 1;
+        const int rb = (st & 1) ? sblock + off : sblock - off;
+        if (rb < 0 || rb >= n_blocks) continue;  // uniform
+        stage_centres(rb);
+        lds_barrier();
+        take_bounds();
+        const uint32_t own = block_mask();
+        n_score += __popc(uint32_t(ballot(lane < 32 && s_cn[lane & 31] < kInf)));
+        if (lane == 0) s_mask[w] = own;
+        lds_barrier();
+        uint32_t uni = 0;
+#pragma unroll
+        for (int g = 0; g < kWgLeaves; ++g) uni |= s_mask[g];
+        uni = uint32_t(uniform_i(int(uni)));
+        if (!uni) continue;
+        // two register sets used in turn: a leaf's loads land in the set that
+        // the next visit reads, so they stay in flight while the current leaf
+        // is processed (no register copy forces an early wait)
         int2 rr_a = make_int2(0, 0), rr_b = make_int2(0, 0);
-        float blo_a[DPL], bhi_a[DPL], blo_b[DPL], bhi_b[DPL], v_a[E], v_b[E];
-#pragma unroll
-        for (int e = 0; e < DPL; ++e) blo_a[e] = bhi_a[e] = blo_b[e] = bhi_b[e] = 0.f;
-#pragma unroll
-        for (int e = 0; e < E; ++e) v_a[e] = v_b[e] = 0.f;
-        // past the last step the fetch repeats the start leaf (in bounds,
-        // never visited): the loads stay unconditional
-        auto leaf_or_start = [&](int st) { return st < steps ? leaf_of(st) : start; };
-        int sc = advance(0);
-        fetch(leaf_or_start(sc), rr_a, blo_a, bhi_a, v_a);
-        while (sc < steps) {
-            int sn = advance(sc + 1);
-            fetch(leaf_or_start(sn), rr_b, blo_b, bhi_b, v_b);
-            visit(rr_a, blo_a, bhi_a, v_a);
-            sc = sn;
-            if (sc >= steps) break;
-            sn = advance(sc + 1);
-            fetch(leaf_or_start(sn), rr_a, blo_a, bhi_a, v_a);
-            visit(rr_b, blo_b, bhi_b, v_b);
-            sc = sn;
+        float v_a[E], v_b[E];
+        int ca = __builtin_ctz(uni);
+        uni &= uni - 1u;
+        fetch(rb * NB + ca, rr_a, v_a);
+        for (;;) {
+            // past the last kept leaf the fetch repeats the current one (in
+            // bounds, never visited): the loads stay unconditional
+            const int cb = uni ? __builtin_ctz(uni) : ca;
+            const bool more_b = uni != 0;
+            uni &= uni - 1u;
+            fetch(rb * NB + cb, rr_b, v_b);
+            visit(rr_a, v_a, (own >> ca) & 1u);
+            if (!more_b) break;
+            const int cc = uni ? __builtin_ctz(uni) : cb;
+            const bool more_c = uni != 0;
+            uni &= uni - 1u;
+            fetch(rb * NB + cc, rr_a, v_a);
+            visit(rr_b, v_b, (own >> cb) & 1u);
+            if (!more_c) break;
+            ca = cc;
         }
-        if (pending) {
-            exchange_bounds();
-            compute(pend_b, pend_base, pend_cnt, pend_own);
-        }
+    }
+    if (pending) {
+        lds_barrier();
+        compute(pend_b, pend_base, pend_cnt, pend_own);
     }
 
     // ---- write-out: FP64 re-score, merge the two half-lists ------------------
