@@ -53,7 +53,8 @@ struct SearchArgs {
     unsigned long long *stats;  // ST_COUNT counters, or NULL; the FP32 kernel with a
                                 // seed adds its second pass's counts to the next
                                 // ST_COUNT
-    uint32_t *wave_log;         // debug: 8 words per wave (ticks, scores, tiles, inserts, passes, leaf)
+    uint32_t *wave_log;         // debug: 8 words per wave (ticks, scores, tiles, inserts, passes, leaf,
+                                // staged tiles and filter candidates of the d = 64 sweep)
     // Score log of the debug kernel (launch_search_valu_debug_d3): one
     // record of kDbgWords words per Score call, or NULL; and the visit order
     // (0: nearer child first, 1: farther child first)

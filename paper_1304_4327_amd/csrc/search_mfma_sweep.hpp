@@ -71,7 +71,12 @@ struct SweepLds {
     static constexpr size_t off_ctr_lam = off_ctr_n + 32 * 4;   // leaf lambdas
     // misc words (kMisc*)
     static constexpr size_t off_misc = off_ctr_lam + 32 * 4;
-    static constexpr size_t bytes = off_misc + 32 * 4;
+    // the sorted block order and keys (the sort itself runs in the tile
+    // buffers, before the sweep uses them)
+    static constexpr int sort_max = int(2 * tile_f / 8) < 2048 ? int(2 * tile_f / 8) : 2048;
+    static constexpr size_t off_okey = off_misc + 32 * 4;
+    static constexpr size_t off_order = off_okey + size_t(sort_max) * 4;
+    static constexpr size_t bytes = off_order + size_t(sort_max) * 2;
 };
 // misc words: each wave's bound and smallest k-th distance, the largest row
 // norm of each wave's staged rows per tile buffer, the same for the block of
@@ -80,6 +85,7 @@ constexpr int kMiscBound = 0;     // [2][kWgLeaves]
 constexpr int kMiscTileMax = 8;   // [2][kWgLeaves]
 constexpr int kMiscCtrMax = 16;   // [kWgLeaves]
 constexpr int kMiscMask = 20;     // [kWgLeaves]
+constexpr int kMiscQlen = 24;     // [kWgLeaves] largest |q - c| of each wave
 
 // Two workgroups per CU (two waves per SIMD) where the lists allow it: each
 // tile's latency chain (staging barrier, dependent MFMAs, LDS reads) is then
@@ -106,6 +112,8 @@ k_search_mfma_sweep(const SearchArgs a) {
     float *s_cl = reinterpret_cast<float *>(smem + L::off_ctr_lam);
     float *s_misc = reinterpret_cast<float *>(smem + L::off_misc);
     uint32_t *s_mask = reinterpret_cast<uint32_t *>(s_misc + kMiscMask);
+    float *s_okey = reinterpret_cast<float *>(smem + L::off_okey);
+    uint16_t *s_order = reinterpret_cast<uint16_t *>(smem + L::off_order);
     // workgroup barrier that waits for this wave's LDS traffic only: the
     // next leaf's global loads stay in flight across it
     auto lds_barrier = [] { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); };
@@ -199,7 +207,7 @@ k_search_mfma_sweep(const SearchArgs a) {
     float bound2 = (a.bound == KNN_BOUND_NONE) ? kInf : seed2;  // this wave's B^2
     float lo_k = kInf;      // min over the wave's queries of D_p[k]^2
     float pair_kth = kInf;  // min of the two half-list k-ths of this query
-    uint32_t n_score = 0, n_tiles = 0, n_ins = 0, n_pass = 0;
+    uint32_t n_score = 0, n_tiles = 0, n_ins = 0, n_pass = 0, n_staged = 0, n_cand = 0;
     uint64_t n_pairs = 0;
 
     auto refresh_bound = [&]() {
@@ -302,6 +310,7 @@ k_search_mfma_sweep(const SearchArgs a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r)
             mask |= (acc[r] <= thr && 8 * (r >> 2) + 4 * h + (r & 3) < cnt) ? (1u << r) : 0u;
+        n_cand += __popc(mask);
         // survivors: one per lane per round, exact FP64 re-score, insert.
         // The round body has no divergent branch: a lane without a survivor
         // re-scores row 0 and inserts +inf (a no-op); the wave issues the
@@ -344,9 +353,75 @@ k_search_mfma_sweep(const SearchArgs a) {
         start = node - a.r_first_leaf;
     }
     const int nl = a.r_first_leaf + 1;  // reference leaves
-    const int n_blocks = (nl + NB - 1) / NB;
+    const int n_blocks = (nl + NB - 1) / NB;  // a power of two
     const int sblock = start / NB;
     const int bsteps = 2 * max(sblock, n_blocks - 1 - sblock) + 1;
+    // Block order.  Up to sort_max blocks: nearest first by the key
+    // k_b = |c - C_b| (1 - 2^-12) - lambda(b), C_b the box centre of the block's
+    // subtree node, which bounds below the distance of every query within R
+    // of c to every point of the block, plus R: d(q, r) >= k_b - R.  In that
+    // order, once k_b exceeds R plus the largest bound of the workgroup, no
+    // later block can hold a neighbour and the sweep ends.  More blocks:
+    // outward in tree order from the start block, no early end.
+    const bool use_sort = n_blocks <= L::sort_max;
+    float R = 0.f;  // largest |q - c| of the workgroup, rounded up
+    if (use_sort) {
+        const float ql = reduce64(valid ? qlen : 0.f, OpMax());
+        if (lane == 0) s_misc[kMiscQlen + w] = ql;
+        uint64_t *s_sort = reinterpret_cast<uint64_t *>(smem + L::off_tile_f);
+        const int first = n_blocks - 1;  // heap index of block 0's node
+        for (int b0 = 0; b0 < n_blocks; b0 += 32) {
+            const int bi = b0 + trow;
+            const bool vb = bi < n_blocks;
+            const float *bx = a.rbox + int64_t(first + (vb ? bi : 0)) * 2 * DP;
+            float sq = 0.f;
+#pragma unroll
+            for (int e = 0; e < E; e += 4) {
+                const float4 lo = *reinterpret_cast<const float4 *>(bx + tcol + e);
+                const float4 hi = *reinterpret_cast<const float4 *>(bx + DP + tcol + e);
+                const float cv[4] = {0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z),
+                                     0.5f * (lo.w + hi.w)};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float df = cv[u] - tc[e + u];
+                    sq = fmaf(df, df, sq);
+                }
+            }
+            sq = reduce8(sq, OpAdd());
+            if (vb && (tid & 7) == 0) {
+                const float key = sqrtf(sq) * (1.0f - 0x1p-12f) - a.rlam[first + bi];
+                s_sort[bi] = (uint64_t(f2key(key)) << 32) | uint32_t(bi);
+            }
+        }
+        // bitonic sort of the n_blocks (key, block) words, ascending
+        for (int size = 2; size <= n_blocks; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                __syncthreads();
+                for (int i = tid; i < n_blocks / 2; i += 256) {
+                    const int lo = 2 * stride * (i / stride) + (i & (stride - 1));
+                    const int hi = lo + stride;
+                    const uint64_t x = s_sort[lo], y = s_sort[hi];
+                    if ((x > y) == ((lo & size) == 0)) {
+                        s_sort[lo] = y;
+                        s_sort[hi] = x;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < n_blocks; i += 256) {
+            const uint64_t x = s_sort[i];
+            s_order[i] = uint16_t(x & 0xffffu);
+            s_okey[i] = key2f(uint32_t(x >> 32));
+        }
+        float rq = 0.f;
+#pragma unroll
+        for (int g = 0; g < kWgLeaves; ++g) rq = fmaxf(rq, s_misc[kMiscQlen + g]);
+        // (|q - c| is an FP32 norm: a relative error of a few 1e-6, far inside
+        // this rounding up)
+        R = uniform_f(rq) * (1.0f + 0x1p-12f);
+        __syncthreads();
+    }
 
     // stage the box centres C = (lo + hi) / 2 of block rb's leaves (row trow =
     // leaf NB rb + trow, this thread's E columns), centred on c and rounded
@@ -473,6 +548,7 @@ k_search_mfma_sweep(const SearchArgs a) {
     bool pend_own = false, pending = false;
     auto visit = [&](int2 rr, const float (&v)[E], bool own) {
         lds_barrier();
+        ++n_staged;
         const int b = pend_b ^ 1;
         const int cnt = uniform_i(rr.y);
         stage(b, cnt, v);
@@ -484,13 +560,29 @@ k_search_mfma_sweep(const SearchArgs a) {
         pend_own = own;
     };
 
-    for (int st = 0; st < bsteps; ++st) {
-        const int off = (st + 1) >> 1;
-        const int rb = (st & 1) ? sblock + off : sblock - off;
-        if (rb < 0 || rb >= n_blocks) continue;  // uniform
+    const int n_steps = use_sort ? n_blocks : bsteps;
+    for (int st = 0; st < n_steps; ++st) {
+        int rb;
+        if (use_sort) {
+            rb = uniform_i(int(s_order[st]));
+        } else {
+            const int off = (st + 1) >> 1;
+            rb = (st & 1) ? sblock + off : sblock - off;
+            if (rb < 0 || rb >= n_blocks) continue;  // uniform
+        }
         stage_centres(rb);
         lds_barrier();
         take_bounds();
+        if (use_sort) {
+            // every query's bound is at most the largest wave bound B (idle
+            // waves publish -inf); the keys are ascending, so when this
+            // block is out of reach, all later ones are too
+            float bw = -kInf;
+#pragma unroll
+            for (int g = 0; g < kWgLeaves; ++g) bw = fmaxf(bw, s_misc[kMiscBound + g]);
+            const float bmax = bw < kInf ? __builtin_amdgcn_sqrtf(fmaxf(bw, 0.f)) * (1.0f + 0x1p-20f) : kInf;
+            if (uniform_f(s_okey[st]) > (bmax + R) * kSlack) break;
+        }
         const uint32_t own = block_mask();
         n_score += __popc(uint32_t(ballot(lane < 32 && s_cn[lane & 31] < kInf)));
         if (lane == 0) s_mask[w] = own;
@@ -592,9 +684,12 @@ k_search_mfma_sweep(const SearchArgs a) {
         }
     }
     if ((a.wave_log || a.stats) && has_leaf) {
-        int ins = n_ins;
+        int ins = n_ins, cand = int(n_cand);
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) ins += __shfl_xor(ins, off);
+        for (int off = 32; off > 0; off >>= 1) {
+            ins += __shfl_xor(ins, off);
+            cand += __shfl_xor(cand, off);
+        }
         if (a.wave_log && lane == 0) {
             uint32_t *wl = a.wave_log + int64_t(slot) * 8;
             wl[0] = 0;
@@ -603,6 +698,8 @@ k_search_mfma_sweep(const SearchArgs a) {
             wl[3] = uint32_t(ins);
             wl[4] = n_pass;
             wl[5] = uint32_t(qleaf);
+            wl[6] = n_staged;
+            wl[7] = uint32_t(cand);
         }
         if (a.stats && lane == 0) {
             atomicAdd(&a.stats[ST_SCORE], (unsigned long long)n_score);
