@@ -37,7 +37,10 @@ namespace knnx {
 namespace {
 
 constexpr int kLocalMax = 1024;  // segments this small finish in one wave
-constexpr int kChunk = 1024;     // elements per block in grid-wide levels
+// elements per block in grid-wide levels: larger chunks for short rows
+// (fewer blocks, so fewer histogram flushes and block-level selection
+// steps per level); long rows keep blocks short for the scatter
+constexpr int chunk_for(int DP) { return DP <= 8 ? 2048 : 1024; }
 constexpr int kBlock = 256;
 
 struct Sel {
@@ -110,16 +113,16 @@ __global__ void k_init(const float *__restrict__ P, int64_t n, int d, float *__r
 }
 
 // ---- grid-wide level: box -----------------------------------------------------
-template <int DP>
+template <int DP, int CH>
 __global__ __launch_bounds__(kBlock) void k_box_level(const float *__restrict__ cur, int d,
                                                       const int2 *__restrict__ range, int node0,
                                                       int bps, uint32_t *__restrict__ boxu) {
     const int seg = blockIdx.x / bps, chunk = blockIdx.x % bps;
     const int2 r = range[node0 + seg];
-    const int e0 = chunk * kChunk, e1 = min(r.y, e0 + kChunk);
+    const int e0 = chunk * CH, e1 = min(r.y, e0 + CH);
     const int t = threadIdx.x, j = t % DP, grp = t / DP;
     constexpr int NG = kBlock / DP;
-    constexpr int IT = kChunk / NG;  // elements per thread
+    constexpr int IT = CH / NG;  // elements per thread
     constexpr int BATCH = IT < 16 ? IT : 16;  // loads issued together
     uint32_t lo = 0xffffffffu, hi = 0u;
     if (j < d) {
@@ -229,7 +232,7 @@ __device__ Sel select_step(const int *__restrict__ H, Sel s) {
 
 // histogram of the current digit of the keys matching the selection prefix;
 // PASS 0 also makes and stores the keys (coordinate of the split dimension)
-template <int DP, int PASS>
+template <int DP, int PASS, int CH>
 __device__ void hist_digit(const float *__restrict__ cur, int2 r, int e0, int e1, int jsplit,
                            uint32_t *__restrict__ keys, Sel s, int *__restrict__ gh) {
     __shared__ int h[kBins];
@@ -239,7 +242,7 @@ __device__ void hist_digit(const float *__restrict__ cur, int2 r, int e0, int e1
     if (count)
         for (int i = threadIdx.x; i < kBins; i += kBlock) h[i] = 0;
     __syncthreads();
-    constexpr int IT = kChunk / kBlock;
+    constexpr int IT = CH / kBlock;
     uint32_t kv[IT];
 #pragma unroll
     for (int q = 0; q < IT; ++q) {
@@ -271,7 +274,7 @@ __device__ inline void clear_share(int *__restrict__ gh, int chunk, int bps) {
 }
 
 // A: split dimension, box, first selection state, digit-0 histogram
-template <int DP>
+template <int DP, int CH>
 __global__ __launch_bounds__(kBlock) void k_level_a(const float *__restrict__ cur, int d,
                                                     const int2 *__restrict__ range, int node0,
                                                     int bps, const uint32_t *__restrict__ boxu,
@@ -329,14 +332,14 @@ __global__ __launch_bounds__(kBlock) void k_level_a(const float *__restrict__ cu
             sel0[seg] = s0;
         }
     }
-    const int e0 = chunk * kChunk, e1 = min(r.y, e0 + kChunk);
-    hist_digit<DP, 0>(cur, r, e0, e1, best, keys, s0, hist0 + int64_t(seg) * kBins);
+    const int e0 = chunk * CH, e1 = min(r.y, e0 + CH);
+    hist_digit<DP, 0, CH>(cur, r, e0, e1, best, keys, s0, hist0 + int64_t(seg) * kBins);
 }
 
 // B, C: selection step on the previous digit, next digit's histogram.
 // B also restores the box accumulators the level has read; C clears the
 // digit-0 histogram.
-template <int PASS>
+template <int PASS, int CH>
 __global__ __launch_bounds__(kBlock) void k_level_bc(const int2 *__restrict__ range, int node0,
                                                      int bps, uint32_t *__restrict__ keys,
                                                      const Sel *__restrict__ sel_in,
@@ -352,11 +355,12 @@ __global__ __launch_bounds__(kBlock) void k_level_bc(const int2 *__restrict__ ra
     if (boxu_reset && chunk == 0 && threadIdx.x < 2 * dp)
         boxu_reset[seg * 2 * dp + threadIdx.x] = threadIdx.x < dp ? 0xffffffffu : 0u;
     if (hist_clear) clear_share(hist_clear + int64_t(seg) * kBins, chunk, bps);
-    const int e0 = chunk * kChunk, e1 = min(r.y, e0 + kChunk);
-    hist_digit<4, PASS>(nullptr, r, e0, e1, 0, keys, s, hist_out + int64_t(seg) * kBins);
+    const int e0 = chunk * CH, e1 = min(r.y, e0 + CH);
+    hist_digit<4, PASS, CH>(nullptr, r, e0, e1, 0, keys, s, hist_out + int64_t(seg) * kBins);
 }
 
 // D: last selection step; counts of keys below / equal to the median key
+template <int CH>
 __global__ __launch_bounds__(kBlock) void k_level_count(const uint32_t *__restrict__ keys,
                                                         const int2 *__restrict__ range,
                                                         int node0, int bps,
@@ -370,10 +374,10 @@ __global__ __launch_bounds__(kBlock) void k_level_count(const uint32_t *__restri
     const Sel s = select_step(hist_in + int64_t(seg) * kBins, sel_in[seg]);
     if (chunk == 0 && threadIdx.x == 0) sel_out[seg] = s;
     clear_share(hist_clear + int64_t(seg) * kBins, chunk, bps);
-    const int e0 = chunk * kChunk, e1 = min(r.y, e0 + kChunk);
+    const int e0 = chunk * CH, e1 = min(r.y, e0 + CH);
     const uint32_t v = s.prefix;
     int nl = 0, ne = 0;
-    constexpr int IT = kChunk / kBlock;
+    constexpr int IT = CH / kBlock;
 #pragma unroll
     for (int q = 0; q < IT; ++q) {
         const int e = e0 + threadIdx.x + q * kBlock;
@@ -406,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_level_count(const uint32_t *__restri
 
 // E: stable partition; for strides <= 8 the two children's box keys are
 // accumulated for the next level (boxu_next != NULL)
-template <int DP>
+template <int DP, int CH>
 __global__ __launch_bounds__(kBlock) void k_level_scatter(const uint32_t *__restrict__ keys,
                                                           const int *__restrict__ idx_in,
                                                           int *__restrict__ idx_out,
@@ -422,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_level_scatter(const uint32_t *__rest
     constexpr bool kBox = DP <= 8;
     const int seg = blockIdx.x / bps, chunk = blockIdx.x % bps;
     const int2 r = range[node0 + seg];
-    const int e0 = chunk * kChunk, e1 = min(r.y, e0 + kChunk);
+    const int e0 = chunk * CH, e1 = min(r.y, e0 + CH);
     const Sel s = sel[seg];
     const uint32_t v = s.prefix;
     const int req = s.rank;  // equal keys that go left
@@ -910,11 +914,12 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
     KNN_HIP(get(&cur, rows * DP));
 
     auto cmax = [&](int lv) { return int((n + (int64_t(1) << lv) - 1) >> lv); };
+    constexpr int CH = chunk_for(DP);
     int n_global = 0, maxseg = 1, maxblk = 1;
     for (int q = 0; q < L && cmax(q) > kLocalMax; ++q) {
         n_global = q + 1;
         maxseg = std::max(maxseg, 1 << q);
-        maxblk = std::max(maxblk, (1 << q) * ((cmax(q) + kChunk - 1) / kChunk));
+        maxblk = std::max(maxblk, (1 << q) * ((cmax(q) + CH - 1) / CH));
     }
     if (n_global > 0) {
         KNN_HIP(get(&idxB, n));
@@ -949,20 +954,20 @@ knn_status build_impl(const float *points, int64_t n, int d, int leaf, hipStream
     Sel *S[4] = {sel, sel + maxseg, sel + 2 * maxseg, sel + 3 * maxseg};
     for (int l = 0; l < n_global; ++l) {
         const int nseg = 1 << l, node0 = nseg - 1;
-        const int bps = (cmax(l) + kChunk - 1) / kChunk;
+        const int bps = (cmax(l) + CH - 1) / CH;
         const int nblk = nseg * bps;
         // the box pass runs at level 0, and at every level for strides > 8
         // (for strides <= 8 the previous level's scatter accumulated it)
-        if (l == 0 || DP > 8) k_box_level<DP><<<nblk, kBlock, 0, s>>>(cur, d, t->range, node0, bps, boxu);
-        k_level_a<DP><<<nblk, kBlock, 0, s>>>(cur, d, t->range, node0, bps, boxu, t->box, t->split_dim,
+        if (l == 0 || DP > 8) k_box_level<DP, CH><<<nblk, kBlock, 0, s>>>(cur, d, t->range, node0, bps, boxu);
+        k_level_a<DP, CH><<<nblk, kBlock, 0, s>>>(cur, d, t->range, node0, bps, boxu, t->box, t->split_dim,
                                              S[0], keys, H[0]);
-        k_level_bc<1><<<nblk, kBlock, 0, s>>>(t->range, node0, bps, keys, S[0], S[1], H[0], H[1],
+        k_level_bc<1, CH><<<nblk, kBlock, 0, s>>>(t->range, node0, bps, keys, S[0], S[1], H[0], H[1],
                                               nullptr, boxu, DP);
-        k_level_bc<2><<<nblk, kBlock, 0, s>>>(t->range, node0, bps, keys, S[1], S[2], H[1], H[2],
+        k_level_bc<2, CH><<<nblk, kBlock, 0, s>>>(t->range, node0, bps, keys, S[1], S[2], H[1], H[2],
                                               H[0], nullptr, DP);
-        k_level_count<<<nblk, kBlock, 0, s>>>(keys, t->range, node0, bps, S[2], S[3], H[2], H[1],
+        k_level_count<CH><<<nblk, kBlock, 0, s>>>(keys, t->range, node0, bps, S[2], S[3], H[2], H[1],
                                               counts);
-        k_level_scatter<DP><<<nblk, kBlock, 0, s>>>(keys, idxA, idxB, cur, nxt, t->range, node0, bps,
+        k_level_scatter<DP, CH><<<nblk, kBlock, 0, s>>>(keys, idxA, idxB, cur, nxt, t->range, node0, bps,
                                                     S[3], counts, H[2], flag, d,
                                                     (DP <= 8 && l + 1 < n_global) ? boxu : nullptr);
         std::swap(idxA, idxB);
