@@ -147,6 +147,26 @@ struct OpMax {
 struct OpMin {
     __device__ float operator()(float a, float b) const { return fminf(a, b); }
 };
+// Insert (x, id) into a k-list held in registers, sorted ascending, K slots,
+// the largest entry dropped (Algorithm 2 keeps each list sorted).  Slot j of
+// the new list is the median of (old[j-1], x, old[j]) (old[-1] = -inf): old
+// slots below x stay, x lands in the first slot it beats, the rest move up
+// one.  Its index follows the value: from slot j - 1 when x < old[j-1], x's
+// when x < old[j], else unchanged, so equal distances keep their older entry
+// first.  x = +inf changes nothing.  Every lane runs it (no divergence).
+template <int K>
+__device__ __forceinline__ void sorted_insert(float (&dist)[K], int (&idx)[K], float x, int id) {
+#pragma unroll
+    for (int j = K - 1; j > 0; --j) {
+        const bool cp = x < dist[j - 1];
+        const bool cj = x < dist[j];
+        idx[j] = cp ? idx[j - 1] : (cj ? id : idx[j]);
+        dist[j] = __builtin_amdgcn_fmed3f(dist[j - 1], x, dist[j]);
+    }
+    idx[0] = x < dist[0] ? id : idx[0];
+    dist[0] = fminf(x, dist[0]);
+}
+
 // bitwise OR of the two values' bit patterns (a 32-bit mask carried in a float)
 struct OpOrBits {
     __device__ float operator()(float a, float b) const {

@@ -152,18 +152,7 @@ __global__ __launch_bounds__(256) void k_search_far(const SearchArgs a) {
         const bool keep = valid && !(sd < point_bound2() * kShrink);
         return ballot(keep) != 0;
     };
-    auto insert = [&](float x, int id) {
-#pragma unroll
-        for (int j = K - 1; j >= 0; --j) {
-            const float dj = key[j];
-            const float dprev = (j > 0) ? key[j - 1] : -kInf;
-            const int iprev = (j > 0) ? idx[j - 1] : -1;
-            const bool cprev = x < dprev;
-            const bool cj = x < dj;
-            key[j] = cprev ? dprev : (cj ? x : dj);
-            idx[j] = cprev ? iprev : (cj ? id : idx[j]);
-        }
-    };
+    auto insert = [&](float x, int id) { sorted_insert<K>(key, idx, x, id); };
     // L after a tile: min and max of the leaf's k-th distances, then the
     // ancestors whose leaves all sit in this wave (one lane level each)
     auto refresh_bound = [&]() {

@@ -160,18 +160,7 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
         bound2 = uniform_f(fminf(b, seed2));
     };
 
-    auto insert = [&](float x, int id) {
-#pragma unroll
-        for (int t = K - 1; t >= 0; --t) {
-            const float dj = dist[t];
-            const float dprev = (t > 0) ? dist[t - 1] : -kInf;
-            const int iprev = (t > 0) ? idx[t - 1] : -1;
-            const bool cprev = x < dprev;
-            const bool cj = x < dj;
-            dist[t] = cprev ? dprev : (cj ? x : dj);
-            idx[t] = cprev ? iprev : (cj ? id : idx[t]);
-        }
-    };
+    auto insert = [&](float x, int id) { sorted_insert<K>(dist, idx, x, id); };
 
     auto tile = [&](int node) {
         ++n_tiles;

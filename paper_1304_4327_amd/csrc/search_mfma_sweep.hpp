@@ -224,18 +224,7 @@ k_search_mfma_sweep(const SearchArgs a) {
         bound2 = uniform_f(fminf(fminf(b, seed2), bound2));
     };
 
-    auto insert = [&](float x, int id) {
-#pragma unroll
-        for (int t = K - 1; t >= 0; --t) {
-            const float dj = dist[t];
-            const float dprev = (t > 0) ? dist[t - 1] : -kInf;
-            const int iprev = (t > 0) ? idx[t - 1] : -1;
-            const bool cprev = x < dprev;
-            const bool cj = x < dj;
-            dist[t] = cprev ? dprev : (cj ? x : dj);
-            idx[t] = cprev ? iprev : (cj ? id : idx[t]);
-        }
-    };
+    auto insert = [&](float x, int id) { sorted_insert<K>(dist, idx, x, id); };
 
     // stage a leaf from prefetched rows v (this thread's E columns of row
     // trow) into tile buffer b: rows past the leaf are zero with an infinite

@@ -270,18 +270,7 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         q2 = p2;
     };
 
-    auto insert = [&](float x, int id) {
-#pragma unroll
-        for (int j = K - 1; j >= 0; --j) {
-            const float dj = dist[j];
-            const float dprev = (j > 0) ? dist[j - 1] : -kInf;
-            const int iprev = (j > 0) ? idx[j - 1] : -1;
-            const bool cprev = x < dprev;
-            const bool cj = x < dj;
-            dist[j] = cprev ? dprev : (cj ? x : dj);
-            idx[j] = cprev ? iprev : (cj ? id : idx[j]);
-        }
-    };
+    auto insert = [&](float x, int id) { sorted_insert<K>(dist, idx, x, id); };
 
     // B(Par(N_q)) terms: the ancestors whose leaves all sit in this wave
     // (aligned sibling groups) contribute min D_p[k] + 2 lambda(ancestor)
