@@ -49,6 +49,8 @@ struct EmstArgs {
     double *best_d2;       // per position: nearest point in another component
     int32_t *best_r;       //   (its position, -1 if none)
     int bound;             // knn_bound
+    int shared;            // 0 in the first round: every component is one
+                           // point, whose own candidate is its bound
     unsigned long long *stats;
 };
 
@@ -56,6 +58,30 @@ __device__ inline unsigned int f32_bits_up(double x) {
     // a float not below x (x >= 0): round to nearest, then one step up
     const float f = (float)x;
     return __float_as_uint(f) + ((double)f < x ? 1u : 0u);
+}
+
+// Minimum per component over a wavefront: points of a component sit mostly
+// in runs of consecutive tree positions, so a segmented minimum over runs of
+// lanes with the same label (Hillis-Steele steps with segment-start flags)
+// leaves one atomic per run instead of one per point (device-scope atomics
+// are the cost of these passes).  Returns true in the last lane of each run
+// of active lanes, with the run's minimum in m.
+template <class T>
+__device__ inline bool run_min(int c, T v, bool act, T &m) {
+    const int lane = threadIdx.x & 63;
+    const int key = act ? c : -1 - lane;  // inactive lanes: a run of their own
+    const int kprev = __shfl_up(key, 1);
+    const int knext = __shfl_down(key, 1);
+    bool f = lane == 0 || kprev != key;  // a run starts within the window
+    m = v;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const T mo = __shfl_up(m, s);
+        const bool fo = __shfl_up(int(f), s) != 0;
+        if (lane >= s && !f) m = min(m, mo);
+        if (lane >= s) f = f || fo;
+    }
+    return act && (lane == 63 || knext != key);
 }
 
 template <int DP, int LG>
@@ -95,7 +121,7 @@ __global__ __launch_bounds__(256) void k_boruvka(const EmstArgs a) {
     auto refresh = [&]() {
         if (a.bound == KNN_BOUND_NONE) return;
         float dp = kInf;
-        if (valid)
+        if (valid && a.shared)
             dp = __uint_as_float(
                 __hip_atomic_load(&a.cbound[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if (bpos >= 0) dp = fminf(dp, __uint_as_float(f32_bits_up(best2)));
@@ -132,6 +158,8 @@ __global__ __launch_bounds__(256) void k_boruvka(const EmstArgs a) {
         const float *rp = a.lpts + int64_t(node - a.first_leaf) * a.leaf_slots * DP;
         n_pairs += uint64_t(cnt) * uint64_t(n_valid);
         bool improved = false;
+        // the filter follows the best candidate within the leaf too
+        float thr = pb * kGamma;
         for (int t0 = 0; t0 < cnt; t0 += CH) {
 #pragma unroll
             for (int cc = 0; cc < CH; ++cc) {
@@ -143,7 +171,7 @@ __global__ __launch_bounds__(256) void k_boruvka(const EmstArgs a) {
                     const float df = q[j] - rp[t * DP + j];
                     sd = fmaf(df, df, sd);
                 }
-                const bool cand = valid && rc != c && sd <= pb * kGamma;
+                const bool cand = valid && rc != c && sd <= thr;
                 if (cand) {
                     const double x = d2_fp64_unfused<DP>(q, rp + t * DP);
                     const int ro = a.perm[base + t];
@@ -152,11 +180,16 @@ __global__ __launch_bounds__(256) void k_boruvka(const EmstArgs a) {
                         bpos = base + t;
                         bperm = ro;
                         improved = true;
+                        thr = fminf(thr, __uint_as_float(f32_bits_up(best2)) * kGamma);
                     }
                 }
             }
         }
-        if (improved && a.bound != KNN_BOUND_NONE) atomicMin(&a.cbound[c], f32_bits_up(best2));
+        if (a.shared && a.bound != KNN_BOUND_NONE) {
+            // one atomic per run of lanes of one component
+            unsigned int m;
+            if (run_min(c, improved ? f32_bits_up(best2) : ~0u, improved, m)) atomicMin(&a.cbound[c], m);
+        }
         refresh();
     };
     tree_walk(a.first_leaf, score, leaf, [](float k0, float k1) { return k1 < k0; });
@@ -222,8 +255,9 @@ __global__ void k_level_comp(int32_t *node_comp, int first, int count) {
 }
 
 __global__ void k_round_reset(unsigned int *cbound, unsigned long long *cbest, unsigned int *cmin,
-                              unsigned int *cmax, int32_t *parent, int n) {
+                              unsigned int *cmax, int32_t *parent, int *unconverged, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *unconverged = 0;
     if (i >= n) return;
     cbound[i] = __float_as_uint(__builtin_inff());
     cbest[i] = ~0ull;
@@ -237,17 +271,28 @@ __global__ void k_round_reset(unsigned int *cbound, unsigned long long *cbest, u
 __global__ void k_seed_bounds(const double *best_d2, const int32_t *best_r, const int32_t *comp,
                               unsigned int *cbound, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int r = best_r[i];
-    if (r >= 0 && comp[r] != comp[i]) atomicMin(&cbound[comp[i]], f32_bits_up(best_d2[i]));
+    const int r = i < n ? best_r[i] : -1;
+    const int c = i < n ? comp[i] : 0;
+    const bool act = r >= 0 && comp[r] != c;
+    unsigned int m;
+    if (run_min(c, act ? f32_bits_up(best_d2[i]) : ~0u, act, m)) atomicMin(&cbound[c], m);
 }
 
-// the component's edge: smallest (length, smaller index, larger index)
+// the component's edge: smallest (length, smaller index, larger index).
+// In the first round every component is one point (labels are the points'
+// own positions): a plain store
 __device__ inline unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
 __global__ void k_pick_len(const double *best_d2, const int32_t *best_r, const int32_t *comp,
-                           unsigned long long *cbest, int n) {
+                           unsigned long long *cbest, int n, int singletons) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && best_r[i] >= 0) atomicMin(&cbest[comp[i]], dbits(best_d2[i]));
+    const bool act = i < n && best_r[i] >= 0;
+    if (singletons) {
+        if (act) cbest[i] = dbits(best_d2[i]);
+        return;
+    }
+    const int c = i < n ? comp[i] : 0;
+    unsigned long long m;
+    if (run_min(c, act ? dbits(best_d2[i]) : ~0ull, act, m)) atomicMin(&cbest[c], m);
 }
 __global__ void k_pick_ends(const double *best_d2, const int32_t *best_r, const int32_t *comp,
                             const int32_t *perm, const unsigned long long *cbest,
@@ -286,12 +331,40 @@ __global__ void k_break_pairs(const unsigned long long *cbest, int32_t *parent, 
     const int o = parent[c];
     if (parent[o] == c && c < o) parent[c] = c;
 }
-__global__ void k_mark_edges(const unsigned long long *cbest, const int32_t *parent, int64_t *flag,
-                             int *count, int n) {
+// a component that hooked keeps its edge; one count per workgroup (all
+// counts go to one word: device-scope atomics on it serialise)
+__global__ __launch_bounds__(1024) void k_mark_edges(const unsigned long long *cbest,
+                                                     const int32_t *parent, int64_t *flag,
+                                                     int *count, int n) {
+    __shared__ int total;
+    if (threadIdx.x == 0) total = 0;
+    __syncthreads();
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n || cbest[c] == ~0ull || parent[c] == c) return;
-    flag[c] = 1;
-    atomicAdd(count, 1);
+    const bool m = c < n && cbest[c] != ~0ull && parent[c] != c;
+    if (m) flag[c] = 1;
+    const uint64_t b = ballot(m);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&total, int(__popcll(b)));
+    __syncthreads();
+    if (threadIdx.x == 0 && total) atomicAdd(count, total);
+}
+// Path compression: every label climbs to its root, one parent per step, in
+// one launch; another thread's update only shortens a path (each value read
+// is an ancestor), so any interleaving is correct.  The hooks form a forest
+// (the strict edge order leaves no cycle but the two-component pairs, which
+// k_break_pairs removed), so each climb ends; a label still below its root
+// after `steps` steps raises *unconverged and the host finishes with
+// pointer jumping.
+__global__ void k_compress(int32_t *parent, int *unconverged, int steps, int n) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    int p = parent[c];
+    for (int it = 0; it < steps; ++it) {
+        const int g = parent[p];
+        if (g == p) break;
+        p = g;
+    }
+    parent[c] = p;
+    if (parent[p] != p) atomicOr(unconverged, 1);
 }
 __global__ void k_jump(int32_t *parent, int n) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -374,12 +447,12 @@ extern "C" knn_status knn_emst(const knn_tree *t, const knn_opts *opts_in, int64
     KNN_HIP(get(&flag, n));
     KNN_HIP(get(&off, size_t(n) + 1));
     KNN_HIP(get(&tops, size_t(scan_scratch(n))));
-    KNN_HIP(get(&count, 1));
+    KNN_HIP(get(&count, 2));  // [0] edges chosen so far, [1] compression unfinished
     if (opts.stats) {
         KNN_HIP(get(&dstats, ST_COUNT));
         KNN_HIP(zero_words(dstats, 2 * ST_COUNT, s));
     }
-    KNN_HIP(zero_words(count, 1, s));
+    KNN_HIP(zero_words(count, 2, s));
     k_init<<<blocks(n), 256, 0, s>>>(comp, flag, n);
     KNN_HIP(hipGetLastError());
 
@@ -426,25 +499,29 @@ extern "C" knn_status knn_emst(const knn_tree *t, const knn_opts *opts_in, int64
                                                       node_comp);
         for (int l = t->depth - 1; l >= 0; --l)
             k_level_comp<<<blocks(1 << l), 256, 0, s>>>(node_comp, (1 << l) - 1, 1 << l);
-        k_round_reset<<<blocks(n), 256, 0, s>>>(cbound, cbest, cmin, cmax, parent, n);
+        k_round_reset<<<blocks(n), 256, 0, s>>>(cbound, cbest, cmin, cmax, parent, count + 1, n);
         if (rounds > 1) k_seed_bounds<<<blocks(n), 256, 0, s>>>(best_d2, best_r, comp, cbound, n);
         KNN_HIP(hipGetLastError());
+        a.shared = rounds > 1 ? 1 : 0;
         KNN_HIP(launch_dp(a, t->dp, lg, grid, s));
-        k_pick_len<<<blocks(n), 256, 0, s>>>(best_d2, best_r, comp, cbest, n);
+        k_pick_len<<<blocks(n), 256, 0, s>>>(best_d2, best_r, comp, cbest, n, rounds == 1 ? 1 : 0);
         k_pick_ends<<<blocks(n), 256, 0, s>>>(best_d2, best_r, comp, t->perm, cbest, cmin, cmax, 0, n);
         k_pick_ends<<<blocks(n), 256, 0, s>>>(best_d2, best_r, comp, t->perm, cbest, cmin, cmax, 1, n);
         k_hook<<<blocks(n), 256, 0, s>>>(best_d2, best_r, comp, t->perm, cbest, cmin, cmax, parent,
                                          eu, ev, ew, n);
         k_break_pairs<<<blocks(n), 256, 0, s>>>(cbest, parent, n);
-        k_mark_edges<<<blocks(n), 256, 0, s>>>(cbest, parent, flag, count, n);
-        for (int j = 0; j < jumps; ++j) k_jump<<<blocks(n), 256, 0, s>>>(parent, n);
+        k_mark_edges<<<(n + 1023) / 1024, 1024, 0, s>>>(cbest, parent, flag, count, n);
+        k_compress<<<blocks(n), 256, 0, s>>>(parent, count + 1, 64, n);
+        KNN_HIP(hipGetLastError());
+        int now[2] = {0, 0};
+        KNN_HIP(hipMemcpyAsync(now, count, sizeof(now), hipMemcpyDeviceToHost, s));
+        KNN_HIP(hipStreamSynchronize(s));
+        if (now[1])
+            for (int j = 0; j < jumps; ++j) k_jump<<<blocks(n), 256, 0, s>>>(parent, n);
         k_relabel<<<blocks(n), 256, 0, s>>>(comp, parent, n);
         KNN_HIP(hipGetLastError());
-        int now = 0;
-        KNN_HIP(hipMemcpyAsync(&now, count, sizeof(int), hipMemcpyDeviceToHost, s));
-        KNN_HIP(hipStreamSynchronize(s));
-        if (now <= edges) return fail(KNN_E_DEVICE, w + ": a round chose no edge");
-        edges = now;
+        if (now[0] <= edges) return fail(KNN_E_DEVICE, w + ": a round chose no edge");
+        edges = now[0];
     }
     KNN_HIP(exclusive_scan(flag, n, off, tops, s));
     k_compact<<<blocks(n), 256, 0, s>>>(flag, off, eu, ev, ew, edge_u, edge_v, edge_w, n);
