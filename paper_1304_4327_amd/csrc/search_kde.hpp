@@ -113,7 +113,13 @@ __global__ __launch_bounds__(256) void k_kde(const KdeArgs a) {
         const int cnt = uniform_i(rr.y);
         const float *rp = a.rlpts + int64_t(node - a.r_first_leaf) * a.r_leaf_slots * DP;
         n_pairs += uint64_t(cnt) * uint64_t(n_valid);
+        // the query's own slot when it lies in this leaf (leave-one-out)
+        const int own = (a.self && qpos >= base && qpos < base + cnt) ? qpos - base : -1;
+        // K = 2^(-d^2 c log2 e): the hardware base-2 exponential, one multiply
+        const float c2 = a.c * 1.44269504088896341f;
         float part = 0.f;
+        // whole batches, no branch per pair: the slots past the leaf's points
+        // hold FLT_MAX, whose squared distance is +inf and kernel value 0
         for (int t0 = 0; t0 < cnt; t0 += CH) {
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
@@ -123,11 +129,11 @@ __global__ __launch_bounds__(256) void k_kde(const KdeArgs a) {
                     const float df = q[j] - rp[(t0 + c) * DP + j];
                     sd = fmaf(df, df, sd);
                 }
-                const bool use = valid && t0 + c < cnt && !(a.self && base + t0 + c == qpos);
-                part += use ? __expf(-sd * a.c) : 0.f;
+                const float e = __builtin_amdgcn_exp2f(-sd * c2);
+                part += (t0 + c == own) ? 0.f : e;
             }
         }
-        f += double(part);
+        if (valid) f += double(part);
     };
     tree_walk_once(a.r_first_leaf, score, leaf, [](float k0, float k1) { return k1 < k0; });
 
