@@ -89,6 +89,10 @@ __global__ __launch_bounds__(256) void k_range(const RangeArgs a) {
         const float *rp = a.rlpts + int64_t(node - a.r_first_leaf) * a.r_leaf_slots * DP;
         n_pairs += uint64_t(cnt) * uint64_t(n_valid);
         for (int t0 = 0; t0 < cnt; t0 += CH) {
+            // a batch of distances first, one wave-wide test: most batches
+            // hold no candidate for any lane
+            bool cand[CH];
+            uint64_t any = 0;
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 float sd = 0.f;
@@ -97,8 +101,13 @@ __global__ __launch_bounds__(256) void k_range(const RangeArgs a) {
                     const float df = q[j] - rp[(t0 + c) * DP + j];
                     sd = fmaf(df, df, sd);
                 }
-                const bool cand = valid && t0 + c < cnt && sd >= a.t_lo && sd <= a.t_hi;
-                if (cand) {
+                cand[c] = valid && t0 + c < cnt && sd >= a.t_lo && sd <= a.t_hi;
+                any |= ballot(cand[c]);
+            }
+            if (!any) continue;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                if (cand[c]) {
                     const double x = d2_fp64_unfused<DP>(q, rp + (t0 + c) * DP);
                     const int pos = base + t0 + c;
                     if (x >= a.lo2 && x <= a.hi2 && !(a.self && pos == qpos)) {
