@@ -187,27 +187,35 @@ __device__ inline int digit_width(int bits) { return bits < kDigitBits ? bits : 
 
 // block-wide: the selection after one more digit (all threads return it)
 __device__ Sel select_step(const int *__restrict__ H, Sel s) {
-    __shared__ int sc[kBlock];
+    __shared__ int wsum[kBlock / 64];
     __shared__ int sbin[2];
     if (s.bits == 0) return s;  // uniform: the same Sel in the whole block
     const int width = digit_width(s.bits), shift = s.bits - width;
     const uint32_t dm = (1u << width) - 1u;
     constexpr int PER = kBins / kBlock;
+    static_assert(PER == 8, "two 16-byte loads per thread");
     int c[PER], sum = 0;
+    {
+        const int4 *h4 = reinterpret_cast<const int4 *>(H + threadIdx.x * PER);
+        const int4 x = h4[0], y = h4[1];
+        c[0] = x.x, c[1] = x.y, c[2] = x.z, c[3] = x.w;
+        c[4] = y.x, c[5] = y.y, c[6] = y.z, c[7] = y.w;
+    }
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        c[q] = H[threadIdx.x * PER + q];
-        sum += c[q];
+    for (int q = 0; q < PER; ++q) sum += c[q];
+    // inclusive prefix of the threads' sums: within each wave by shuffles,
+    // then the sums of the waves before
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
     }
-    sc[threadIdx.x] = sum;
+    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        const int v = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
-        __syncthreads();
-        sc[threadIdx.x] += v;
-        __syncthreads();
-    }
-    const int incl = sc[threadIdx.x], excl = incl - sum;
+    for (int q = 0; q < wv; ++q) incl += wsum[q];
+    const int excl = incl - sum;
     if (excl <= s.rank && s.rank < incl) {
         int rem = s.rank - excl, bin = threadIdx.x * PER;
 #pragma unroll
@@ -226,7 +234,7 @@ __device__ Sel select_step(const int *__restrict__ H, Sel s) {
     r.mask |= dm << shift;
     r.rank = sbin[1];
     r.bits = shift;
-    __syncthreads();  // sc / sbin are reused by the next step
+    __syncthreads();  // wsum / sbin are reused by the next step
     return r;
 }
 
