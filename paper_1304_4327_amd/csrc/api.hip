@@ -189,6 +189,10 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
             return fail(KNN_E_UNSUPPORTED, "knn_search: BF16 tiles need leaves of <= 32 points");
         lpl_log2 = 6;  // one query leaf per wave
     }
+    // BF16 at stride 16 or 32 with lists of <= 16: the traversal kernel with
+    // matrix-core tiles (two query leaves per wave, its own seeded pass)
+    const bool mt = bf16 && !dbg && (ref->dp == 16 || ref->dp == 32) && K <= 16;
+    if (mt) lpl_log2 = 5;
     const int NG = 64 >> lpl_log2;
     const int nq_leaves = int(qt->n_leaves);
     if (dbg && (ref->d != 3 || bf16 || opts.seed_radius || K > 16))
@@ -303,13 +307,15 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
         KNN_HIP(hipEventRecord(ev[0], s));
     }
     KNN_HIP(dbg    ? launch_search_valu_debug_d3(a, K, grid, s)
+            : mt   ? (ref->dp == 16 ? launch_search_mt_d16(a, K, grid, s)
+                                    : launch_search_mt_d32(a, K, grid, s))
             : bf16 ? launch_mfma(a, ref->dp, K, grid, s)
                    : launch_valu(a, ref->d, K, grid, s));
     if (timing) KNN_HIP(hipEventRecord(ev[1], s));
     if (opts.seed_radius) {
         k_count_flags<<<(nq_leaves + 255) / 256, 256, 0, s>>>(fb_flag, nq_leaves, fb_count);
     }
-    if (opts.seed_radius && bf16) {
+    if (opts.seed_radius && bf16 && !mt) {
         // fallback of the BF16 kernels: the listed leaves again, from empty
         // lists, with the proven bound of the first pass as their initial
         // bound (the FP32 kernel runs this second pass in the same wave)

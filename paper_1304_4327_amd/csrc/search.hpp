@@ -103,6 +103,13 @@ hipError_t launch_search_valu_seeded_d64(const SearchArgs &a, int K, int grid, h
 // (search_debug_d3.hip); lists up to 16
 hipError_t launch_search_valu_debug_d3(const SearchArgs &a, int K, int grid, hipStream_t s);
 
+// the traversal kernel with BF16 matrix-core BaseCase tiles
+// (search_mt_d*.hip): 16 or 32 computed dimensions, two query leaves per wave
+// (lpl_log2 = 5), reference leaves of <= 32 points, K <= 16; the seeded form
+// when a.seed is set
+hipError_t launch_search_mt_d16(const SearchArgs &a, int K, int grid, hipStream_t s);
+hipError_t launch_search_mt_d32(const SearchArgs &a, int K, int grid, hipStream_t s);
+
 // BF16 MFMA kernels (search_mfma_d*.hip), stride 16, 32 or 64
 hipError_t launch_search_mfma_dp16(const SearchArgs &a, int K, int grid, hipStream_t s);
 hipError_t launch_search_mfma_dp32(const SearchArgs &a, int K, int grid, hipStream_t s);

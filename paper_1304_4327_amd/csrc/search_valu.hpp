@@ -48,8 +48,19 @@
 //     the same wave, from empty lists, with the proven bound of the first
 //     pass.
 // The plain form carries none of the other two forms' state.
-#pragma once
+//
+// Matrix-core tiles (MT, d = 16 or 32, two leaves of 17..32 points per wave,
+// lists of up to 16): the same walk, Score and bounds; a reference leaf's
+// BaseCase distances come from the BF16 tile of bf16_tile.hpp, centred on
+// the union box centre c of the wave's two leaves, one product per query leaf
+// (the 32 queries of leaf g are its columns).  Lane l is then both query
+// l % 32 of leaf l / 32 and column l % 32 of half l / 32 of the products, so
+// it holds half of its own query's 32 values and takes the other half from
+// lane l ^ 32.  A row is a candidate when its value minus the proven margin
+// beats min(D_p[k], B); candidates are re-scored in FP64 before they may
+// enter the list, so the lists are those of the FP32 form.
 
+#include "bf16_tile.hpp"
 #include "search.hpp"
 
 namespace knnx {
@@ -71,12 +82,17 @@ __device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p
 
 constexpr int stride_for(int D) { return D <= 4 ? 4 : D <= 8 ? 8 : D <= 16 ? 16 : D <= 32 ? 32 : 64; }
 
-template <int D>
+// FRESH: the query is converted at each call (an empty asm statement hides
+// its value), so that the compiler keeps no FP64 copy of it in registers
+// across the walk
+template <int D, bool FRESH = false>
 __device__ inline double d2_fp64(const float (&q)[D], const float *r) {
     double s = 0.0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        double t = (double)q[j] - (double)r[j];
+        float qj = q[j];
+        if constexpr (FRESH) asm volatile("" : "+v"(qj));
+        double t = (double)qj - (double)r[j];
         s = fma(t, t, s);
     }
     return s;
@@ -84,10 +100,12 @@ __device__ inline double d2_fp64(const float (&q)[D], const float *r) {
 
 enum : int { kValuPlain = 0, kValuDebug = 1, kValuSeeded = 2 };
 
-template <int D, int K, int LG, int MODE = kValuPlain>
+template <int D, int K, int LG, int MODE = kValuPlain, bool MT = false>
 __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     constexpr bool DBG = MODE == kValuDebug;
     constexpr bool SEEDED = MODE == kValuSeeded;
+    static_assert(!MT || ((D == 16 || D == 32) && LG == 5 && !DBG),
+                  "matrix-core tiles: d = 16 or 32, two leaves of <= 32 points per wave");
     constexpr int DP = stride_for(D);
     constexpr bool RESCORE = D > 8;
     constexpr float kInf = __builtin_inff();
@@ -157,6 +175,38 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         }
         ulo[0] = lo;
         uhi[0] = hi;
+    }
+    // MT: the centre c (union box centre), this lane's centre values at its
+    // operand dimensions, |q - c| of its own query and the query operands
+    // -2 (q - c) of both leaves (column l % 32 of leaf g is the query of lane
+    // 32 g + l % 32)
+    constexpr int S = MT ? DP / 16 : 1;
+    const int hh = lane >> 5, jj = lane & 31;
+    [[maybe_unused]] float tcen[S * 8];
+    [[maybe_unused]] bf16x8_t bq0[S], bq1[S];
+    [[maybe_unused]] float qn_mt = 0.f, qlen_mt = 0.f;
+    if constexpr (MT) {
+        const float cl = lane < DP ? 0.5f * (ulo[0] + uhi[0]) : 0.f;
+#pragma unroll
+        for (int d0 = 0; d0 < D; ++d0) {
+            const float df = q[d0] - __shfl(cl, d0);
+            qn_mt = fmaf(df, df, qn_mt);
+        }
+        qlen_mt = sqrtf(qn_mt);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int da = s * 16 + e, db = da + 8;
+                const float ca = __shfl(cl, da), cb = __shfl(cl, db);
+                const float c = hh ? cb : ca;
+                tcen[s * 8 + e] = c;
+                const float a0 = __shfl(q[da], jj), b0 = __shfl(q[db], jj);
+                const float a1 = __shfl(q[da], 32 + jj), b1 = __shfl(q[db], 32 + jj);
+                bq0[s][e] = (__bf16)(-2.0f * ((hh ? b0 : a0) - c));
+                bq1[s][e] = (__bf16)(-2.0f * ((hh ? b1 : a1) - c));
+            }
+        }
     }
     const float lam2 = has_leaf ? 2.0f * a.qlam[qnode] : 0.f;
     // seeded form: a seed is only a pruning radius; NaN or negative values
@@ -332,6 +382,87 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
         const int cnt = uniform_i(rr.y);
         const float *rp = a.rlpts + int64_t(node - a.r_first_leaf) * a.r_leaf_slots * DP;
         n_pairs += uint64_t(cnt) * uint64_t(n_valid);
+        if constexpr (MT) {
+            // the wave's row norms, the accumulators' initial values
+            __shared__ float s_rn[4][32];
+            float *my_rn = s_rn[threadIdx.x >> 6];
+            // reference operand: row jj, the dimensions of half hh, centred
+            const bool vr = jj < cnt;
+            const float *row = rp + (vr ? jj : 0) * DP + hh * 8;
+            bf16x8_t ar[S];
+            float rn = 0.f;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const float4 x0 = *reinterpret_cast<const float4 *>(row + s * 16);
+                const float4 x1 = *reinterpret_cast<const float4 *>(row + s * 16 + 4);
+                const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float rd = vr ? xv[e] - tcen[s * 8 + e] : 0.f;
+                    rn = fmaf(rd, rd, rn);
+                    ar[s][e] = (__bf16)rd;
+                }
+            }
+            rn += __shfl_xor(rn, 32);  // the row's whole norm
+            // largest |r - c| of the tile (hardware square root, nudged up:
+            // the margin only needs an upper bound)
+            const float rlen =
+                __builtin_amdgcn_sqrtf(uniform_f(reduce32(vr ? rn : 0.f, OpMax()))) * (1.0f + 0x1p-20f);
+            if (hh == 0) my_rn[jj] = vr ? rn : kInf;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            f32x16_t acc0, acc1;
+#pragma unroll
+            for (int g4 = 0; g4 < 4; ++g4) {
+                const float4 v = *reinterpret_cast<const float4 *>(&my_rn[g4 * 8 + hh * 4]);
+                acc0[g4 * 4 + 0] = acc1[g4 * 4 + 0] = v.x;
+                acc0[g4 * 4 + 1] = acc1[g4 * 4 + 1] = v.y;
+                acc0[g4 * 4 + 2] = acc1[g4 * 4 + 2] = v.z;
+                acc0[g4 * 4 + 3] = acc1[g4 * 4 + 3] = v.w;
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[s], bq0[s], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[s], bq1[s], acc1, 0, 0, 0);
+            }
+            // this lane's query: rows of half hh from its own leaf's product,
+            // rows of the other half from lane ^ 32; keep D < T - |q'|^2 + M
+            // (the margin is 1.25 times the proven bound, so the strict test
+            // keeps every row the bound admits).  T is capped at FLT_MAX:
+            // rows past the tile hold +inf and never pass, valid rows always
+            // do while a list is not full.  Bit r: the sign of D - thr.
+            const float marg = bf16_margin<DP>(qlen_mt, rlen);
+            const float thr =
+                valid ? fminf(fminf(dist[K - 1], bound2) * kSlack - qn_mt + marg, 0x1.fffffep127f) : -kInf;
+            uint32_t mask = 0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float own = hh ? acc1[r] : acc0[r];
+                const float oth = __shfl_xor(hh ? acc0[r] : acc1[r], 32);
+                mask |= (__float_as_uint(own - thr) >> 31) << r;
+                mask |= (__float_as_uint(oth - thr) >> 31) << (16 + r);
+            }
+            if (!ballot(mask != 0)) return;  // lists unchanged, and so the bound
+            // survivors: one per lane per round, FP64 re-score, insert (a lane
+            // without one re-scores row 0 and inserts +inf, a no-op)
+#pragma unroll 1
+            for (int pass = 0; pass < 32; ++pass) {
+                if (!ballot(mask != 0)) break;
+                ++n_pass;
+                const bool has = mask != 0;
+                const int b = has ? __builtin_ctz(mask) : 0;
+                mask &= mask - 1u;
+                const int rb = b & 15, hb = b < 16 ? hh : 1 - hh;
+                const int rw = 8 * (rb >> 2) + 4 * hb + (rb & 3);
+                const float x = (float)d2_fp64<D, true>(q, rp + rw * DP);
+                const bool ins = has && x < dist[K - 1];
+                n_ins += ins ? 1u : 0u;
+                insert(ins ? x : kInf, base + rw);
+            }
+            refresh_bound();
+            return;
+        }
         const float bnd = bound2 * kSlack;
         uint32_t r0 = 0, r1 = 0, r2 = 0;
         if constexpr (DP <= 4) {
@@ -625,6 +756,22 @@ hipError_t launch_search_valu(const SearchArgs &a, int K, int grid, hipStream_t 
         case 64: return launch_search_valu_k<D, 64, MODE>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+// matrix-core tiles: two leaves per wave (LG = 5), lists of up to 16
+template <int D, int MODE = kValuPlain>
+hipError_t launch_search_valu_mt(const SearchArgs &a, int K, int grid, hipStream_t s) {
+    if (a.lpl_log2 != 5 || a.r_leaf_slots > 32) return hipErrorInvalidValue;
+    switch (K) {
+        case 4: k_search_valu<D, 4, 5, MODE, true><<<grid, 256, 0, s>>>(a); break;
+        case 5: k_search_valu<D, 5, 5, MODE, true><<<grid, 256, 0, s>>>(a); break;
+        case 8: k_search_valu<D, 8, 5, MODE, true><<<grid, 256, 0, s>>>(a); break;
+        case 10: k_search_valu<D, 10, 5, MODE, true><<<grid, 256, 0, s>>>(a); break;
+        case 11: k_search_valu<D, 11, 5, MODE, true><<<grid, 256, 0, s>>>(a); break;
+        case 16: k_search_valu<D, 16, 5, MODE, true><<<grid, 256, 0, s>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace knnx

@@ -151,7 +151,7 @@ def test_bf16_tiles_match_oracle(name, scale, bound):
     _check(ref, q, k, gi, gd)
 
 
-@pytest.mark.parametrize("d,k", [(9, 1), (16, 7), (33, 20), (64, 64)])
+@pytest.mark.parametrize("d,k", [(9, 1), (16, 7), (24, 10), (32, 15), (33, 20), (64, 64)])
 def test_bf16_dims_and_self(d, k):
     rng = np.random.default_rng(d * 100 + k)
     ref = (rng.standard_normal((3000, d)) * rng.uniform(0.1, 3.0, d)).astype(np.float32)
@@ -183,11 +183,23 @@ def test_bf16_sweep_small_and_idle_waves(n_ref, n_q, k, leaf):
         assert np.array_equal(gi, gi2) and np.array_equal(gd, gd2)
 
 
-def test_bf16_same_answer_as_fp32():
-    ref, q, k, leaf = datagen.make("manifold4m_d16_k10", scale=0.004)
+@pytest.mark.parametrize("d", [16, 32])
+def test_bf16_same_answer_as_fp32(d):
+    """Stride 16 and 32 with lists of <= 16 run the traversal kernel with
+    matrix-core tiles: every list equals the FP32 kernel's bit for bit and
+    passes the oracle check."""
+    if d == 16:
+        ref, q, k, leaf = datagen.make("manifold4m_d16_k10", scale=0.004)
+    else:
+        rng = np.random.default_rng(32)
+        basis = rng.standard_normal((8, 32))
+        ref = (rng.random((20000, 8)) @ basis + 0.02 * rng.standard_normal((20000, 32))).astype(np.float32)
+        q = (rng.random((3000, 8)) @ basis + 0.02 * rng.standard_normal((3000, 32))).astype(np.float32)
+        k, leaf = 10, 32
     a = _search(ref, q, k, leaf, precision="fp32")
     b = _search(ref, q, k, leaf, precision="bf16")
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    _check(ref, q, k, b[0], b[1])
 
 
 def test_bf16_low_dim_unsupported():
