@@ -100,8 +100,8 @@ __device__ inline double d2_fp64(const float (&q)[D], const float *r) {
 
 enum : int { kValuPlain = 0, kValuDebug = 1, kValuSeeded = 2 };
 
-template <int D, int K, int LG, int MODE = kValuPlain, bool MT = false>
-__global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
+template <int D, int K, int LG, int MODE, bool MT>
+__device__ __forceinline__ void search_valu_body(const SearchArgs &a) {
     constexpr bool DBG = MODE == kValuDebug;
     constexpr bool SEEDED = MODE == kValuSeeded;
     static_assert(!MT || ((D == 16 || D == 32) && LG == 5 && !DBG),
@@ -727,6 +727,20 @@ __global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
     }
 }
 
+template <int D, int K, int LG, int MODE = kValuPlain>
+__global__ __launch_bounds__(256) void k_search_valu(const SearchArgs a) {
+    search_valu_body<D, K, LG, MODE, false>(a);
+}
+
+// matrix-core tiles; at d = 16 the register budget of three waves per SIMD
+// keeps the accumulators in ordinary registers (four waves fit), at d = 32
+// it would spill
+template <int D, int K, int MODE = kValuPlain>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 16 ? 3 : 1))) void
+k_search_valu_mt(const SearchArgs a) {
+    search_valu_body<D, K, 5, MODE, true>(a);
+}
+
 template <int D, int K, int MODE = kValuPlain>
 hipError_t launch_search_valu_k(const SearchArgs &a, int grid, hipStream_t s) {
     switch (a.lpl_log2) {
@@ -763,12 +777,12 @@ template <int D, int MODE = kValuPlain>
 hipError_t launch_search_valu_mt(const SearchArgs &a, int K, int grid, hipStream_t s) {
     if (a.lpl_log2 != 5 || a.r_leaf_slots > 32) return hipErrorInvalidValue;
     switch (K) {
-        case 4: k_search_valu<D, 4, 5, MODE, true><<<grid, 256, 0, s>>>(a); break;
-        case 5: k_search_valu<D, 5, 5, MODE, true><<<grid, 256, 0, s>>>(a); break;
-        case 8: k_search_valu<D, 8, 5, MODE, true><<<grid, 256, 0, s>>>(a); break;
-        case 10: k_search_valu<D, 10, 5, MODE, true><<<grid, 256, 0, s>>>(a); break;
-        case 11: k_search_valu<D, 11, 5, MODE, true><<<grid, 256, 0, s>>>(a); break;
-        case 16: k_search_valu<D, 16, 5, MODE, true><<<grid, 256, 0, s>>>(a); break;
+        case 4: k_search_valu_mt<D, 4, MODE><<<grid, 256, 0, s>>>(a); break;
+        case 5: k_search_valu_mt<D, 5, MODE><<<grid, 256, 0, s>>>(a); break;
+        case 8: k_search_valu_mt<D, 8, MODE><<<grid, 256, 0, s>>>(a); break;
+        case 10: k_search_valu_mt<D, 10, MODE><<<grid, 256, 0, s>>>(a); break;
+        case 11: k_search_valu_mt<D, 11, MODE><<<grid, 256, 0, s>>>(a); break;
+        case 16: k_search_valu_mt<D, 16, MODE><<<grid, 256, 0, s>>>(a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
