@@ -190,24 +190,24 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
         }
         acc = bf16_tile_product<DP>(ar, bq, acc);
         wave_sync();  // s_rn is rewritten by the next tile
-        // keep D <= T - |q'|^2 + M
+        // keep D < T - |q'|^2 + M (the margin is 1.25 times the proven
+        // bound, so the strict test keeps every row the bound admits); T is
+        // capped at FLT_MAX: rows past the leaf hold +inf and never pass,
+        // valid rows always do while a list is not full
         const float lim = fminf(pair_kth, bound2) * kSlack;
         const float marg = bf16_margin<DP>(qlen, rlen);
-        const float thr = lim - qn + marg;
+        const float thr = valid ? fminf(lim - qn + marg, 0x1.fffffep127f) : -kInf;
         // most tiles have no candidate at all: one test on the smallest value
         // of each lane skips the per-row mask, the survivor rounds and the
-        // bound refresh (the lists and so the bounds are unchanged); rows past
-        // the leaf hold +inf and are masked below when the threshold is +inf
+        // bound refresh (the lists and so the bounds are unchanged)
         float amin = acc[0];
 #pragma unroll
         for (int r = 1; r < 16; ++r) amin = fminf(amin, acc[r]);
-        if (!ballot(valid && amin <= thr)) return;
+        if (!ballot(amin < thr)) return;
+        // bit r: the sign of D - thr (no per-bit constants in registers)
         uint32_t mask = 0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = 8 * (r / 4) + 4 * h + (r % 4);
-            mask |= (valid && row < cnt && acc[r] <= thr) ? (1u << r) : 0u;
-        }
+        for (int r = 0; r < 16; ++r) mask |= (__float_as_uint(acc[r] - thr) >> 31) << r;
         // survivors: one per lane per round, exact FP64 re-score, insert
         const float *qp = a.qpts + int64_t(qpos) * DP;
         // (unrolled: a loop here carried the lists and made the compiler

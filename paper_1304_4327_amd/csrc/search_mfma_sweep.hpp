@@ -282,23 +282,24 @@ k_search_mfma_sweep(const SearchArgs a) {
             const bf16x8_t ar = *reinterpret_cast<const bf16x8_t *>(arow + s * 16);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, bq[s], acc, 0, 0, 0);
         }
-        // keep D <= T - |q'|^2 + M
+        // keep D < T - |q'|^2 + M (the margin is 1.25 times the proven
+        // bound, so the strict test keeps every row the bound admits); T is
+        // capped at FLT_MAX: rows past the leaf hold +inf and never pass,
+        // valid rows always do while a list is not full
         const float lim = fminf(pair_kth, bound2) * kSlack;
         const float marg = bf16_margin<DP>(qlen, rlen);
-        const float thr = valid ? lim - qn + marg : -kInf;
+        const float thr = valid ? fminf(lim - qn + marg, 0x1.fffffep127f) : -kInf;
         // most tiles have no candidate at all: one test on the smallest value
         // of each lane skips the per-row mask, the survivor rounds and the
         // bound refresh (the lists and so the bounds are unchanged)
         float amin = acc[0];
 #pragma unroll
         for (int r = 1; r < 16; ++r) amin = fminf(amin, acc[r]);
-        if (!ballot(amin <= thr)) return;
-        // rows past the leaf never count: their +inf would pass a +inf
-        // threshold (empty lists)
+        if (!ballot(amin < thr)) return;
+        // bit r: the sign of D - thr (no per-bit constants in registers)
         uint32_t mask = 0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-            mask |= (acc[r] <= thr && 8 * (r >> 2) + 4 * h + (r & 3) < cnt) ? (1u << r) : 0u;
+        for (int r = 0; r < 16; ++r) mask |= (__float_as_uint(acc[r] - thr) >> 31) << r;
         n_cand += __popc(mask);
         // survivors: one per lane per round, exact FP64 re-score, insert.
         // The round body has no divergent branch: a lane without a survivor
