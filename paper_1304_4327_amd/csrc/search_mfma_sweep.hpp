@@ -497,13 +497,16 @@ k_search_mfma_sweep(const SearchArgs a) {
         const float lim = fminf(pair_kth, bound2);
         const float bp = lim < kInf ? __builtin_amdgcn_sqrtf(fmaxf(lim, 0.f)) * (1.0f + 0x1p-20f) : kInf;
         const float low0 = qn - bf16_margin<DP>(qlen, clen);
-        uint32_t m = 0;
+        // bit r of m16: the sign of (b_p + lambda)^2 (1 + 2^-16) - low end
+        // clear (keep); then nibble g of m16 moves to rows 8 g + 4 h .. + 3
+        uint32_t m16 = 0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const float t = bp + lam[r];
-            const bool keep = !(acc[r] + low0 > t * t * kSlack);
-            m |= keep ? (1u << (8 * (r >> 2) + 4 * h + (r & 3))) : 0u;
+            m16 |= ((~__float_as_uint(t * t * kSlack - (acc[r] + low0))) >> 31) << r;
         }
+        uint32_t m = (m16 & 0xfu) | ((m16 & 0xf0u) << 4) | ((m16 & 0xf00u) << 8) | ((m16 & 0xf000u) << 12);
+        m <<= 4 * h;
         // without pruning every leaf of the block is evaluated
         m = !valid ? 0u : a.bound == KNN_BOUND_NONE ? 0xffffffffu : m;
         // OR over the wave
