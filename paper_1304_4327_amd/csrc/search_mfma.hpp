@@ -126,7 +126,10 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
         idx[t] = -1;
     }
     float bound2 = (a.bound == KNN_BOUND_NONE) ? kInf : seed2;
-    float pair_kth = kInf;  // min of the two half-list k-ths of this query
+    // this query's k-th distance so far: the k-th smallest entry of its two
+    // half-lists together (lists of exactly k entries), else the smaller of
+    // the two half-list k-ths (an upper bound of it)
+    float pair_kth = kInf;
     uint32_t n_score = 0, n_tiles = 0, n_ins = 0, n_pass = 0;
     uint64_t n_pairs = 0;
 
@@ -147,7 +150,19 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
     auto keep_of = [&](float dmin2) { return !(dmin2 > bound2 * kSlack); };
 
     auto refresh_bound = [&]() {
-        pair_kth = xor32_op(dist[K - 1], OpMin());
+        if (kk == K) {
+            // k-th smallest of two sorted lists A (own) and B (lane ^ 32):
+            // min over i of max(A[i-1], B[k-1-i]), i entries taken from A
+            float m = dist[K - 1];  // i = k
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const float y = __shfl_xor(dist[K - 1 - i], 32);
+                m = fminf(m, i > 0 ? fmaxf(dist[i - 1], y) : y);
+            }
+            pair_kth = m;
+        } else {
+            pair_kth = xor32_op(dist[K - 1], OpMin());
+        }
         if (a.bound == KNN_BOUND_NONE) return;
         const float hi = reduce32(valid ? pair_kth : -kInf, OpMax());
         const float lo = reduce32(valid ? pair_kth : kInf, OpMin());

@@ -151,7 +151,7 @@ def test_bf16_tiles_match_oracle(name, scale, bound):
     _check(ref, q, k, gi, gd)
 
 
-@pytest.mark.parametrize("d,k", [(9, 1), (16, 7), (24, 10), (32, 15), (33, 20), (64, 64)])
+@pytest.mark.parametrize("d,k", [(9, 1), (16, 7), (24, 10), (32, 15), (20, 32), (33, 20), (64, 64)])
 def test_bf16_dims_and_self(d, k):
     rng = np.random.default_rng(d * 100 + k)
     ref = (rng.standard_normal((3000, d)) * rng.uniform(0.1, 3.0, d)).astype(np.float32)
