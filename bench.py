@@ -479,7 +479,13 @@ def main():
         # of 16 count as issued work, the algorithmic count uses d)
         flop_per_pair = 2 * d
         peak = PEAKS["bf16_mfma_tflops"]
-        bound_kind, kname = "mfma", "k_search_mfma"
+        # the BF16 kernel the library picks: the leaf sweep at stride 64,
+        # the traversal kernel with matrix-core tiles at stride 16 / 32 with
+        # lists of <= 16, else the per-leaf MFMA kernel
+        stride = 16 if d <= 16 else 32 if d <= 32 else 64
+        bound_kind = "mfma"
+        kname = ("k_search_mfma_sweep" if stride == 64 else
+                 "k_search_valu_mt" if k + (1 if self_mode else 0) <= 16 else "k_search_mfma")
     else:
         flop_per_pair = 3 * d - 1
         peak = PEAKS["fp32_vector_tflops"]

@@ -147,6 +147,15 @@ struct OpMax {
 struct OpMin {
     __device__ float operator()(float a, float b) const { return fminf(a, b); }
 };
+// Sum over the lanes 0 .. DP-1 that hold one dimension each (the other lanes
+// hold zeros), complete in lane 0: within one row of 16 lanes by DPP alone,
+// the crossbar only for the rows beyond.
+template <int DP>
+__device__ inline float sum_dim_lanes(float v) {
+    if constexpr (DP <= 16) return reduce16(v, OpAdd());
+    else if constexpr (DP <= 32) return reduce32(v, OpAdd());
+    else return reduce64(v, OpAdd());
+}
 // Insert (x, id) into a k-list held in registers, sorted ascending, K slots,
 // the largest entry dropped (Algorithm 2 keeps each list sorted).  Slot j of
 // the new list is the median of (old[j-1], x, old[j]) (old[-1] = -inf): old

@@ -145,8 +145,7 @@ __global__ __launch_bounds__(256) void k_search_far(const SearchArgs a) {
             const float lo = lane < DP ? b[lane] : 0.f, hi = lane < DP ? b[DP + lane] : 0.f;
             const float us = fmaxf(fmaxf(uhi[0] - lo, hi - ulo[0]), 0.0f);
             u = us * us;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off);
+            u = sum_dim_lanes<DP>(u);
         }
         key_out = uniform_f(u);
         const bool keep = valid && !(sd < point_bound2() * kShrink);

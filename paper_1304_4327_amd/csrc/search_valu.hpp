@@ -256,8 +256,7 @@ __device__ __forceinline__ void search_valu_body(const SearchArgs &a) {
             const float lo = lane < DP ? b[lane] : 0.f, hi = lane < DP ? b[DP + lane] : 0.f;
             const float ug = fmaxf(fmaxf(lo - uhi[0], ulo[0] - hi), 0.0f);
             u = ug * ug;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off);
+            u = sum_dim_lanes<DP>(u);
         }
         const bool keep = valid && !(sd > point_bound2() * kSlack);
         key_out = uniform_f(u);
