@@ -82,16 +82,18 @@ __device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p
 
 constexpr int stride_for(int D) { return D <= 4 ? 4 : D <= 8 ? 8 : D <= 16 ? 16 : D <= 32 ? 32 : 64; }
 
-// FRESH: the query is converted at each call (an empty asm statement hides
-// its value), so that the compiler keeps no FP64 copy of it in registers
-// across the walk
+// FRESH: the query is converted at each call (an empty asm statement that
+// also reads the row address hides its value), so that the compiler keeps no
+// FP64 copy of it in registers across the walk.  The statement is not
+// volatile and touches no memory: the walk's wave-uniform loads stay scalar.
 template <int D, bool FRESH = false>
 __device__ inline double d2_fp64(const float (&q)[D], const float *r) {
     double s = 0.0;
+    const uint32_t salt = uint32_t(reinterpret_cast<uintptr_t>(r));
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         float qj = q[j];
-        if constexpr (FRESH) asm volatile("" : "+v"(qj));
+        if constexpr (FRESH) asm("" : "+v"(qj) : "v"(salt));
         double t = (double)qj - (double)r[j];
         s = fma(t, t, s);
     }
@@ -382,9 +384,6 @@ __device__ __forceinline__ void search_valu_body(const SearchArgs &a) {
         const float *rp = a.rlpts + int64_t(node - a.r_first_leaf) * a.r_leaf_slots * DP;
         n_pairs += uint64_t(cnt) * uint64_t(n_valid);
         if constexpr (MT) {
-            // the wave's row norms, the accumulators' initial values
-            __shared__ float s_rn[4][32];
-            float *my_rn = s_rn[threadIdx.x >> 6];
             // reference operand: row jj, the dimensions of half hh, centred
             const bool vr = jj < cnt;
             const float *row = rp + (vr ? jj : 0) * DP + hh * 8;
@@ -407,19 +406,25 @@ __device__ __forceinline__ void search_valu_body(const SearchArgs &a) {
             // the margin only needs an upper bound)
             const float rlen =
                 __builtin_amdgcn_sqrtf(uniform_f(reduce32(vr ? rn : 0.f, OpMax()))) * (1.0f + 0x1p-20f);
-            if (hh == 0) my_rn[jj] = vr ? rn : kInf;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            f32x16_t acc0, acc1;
-#pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) {
-                const float4 v = *reinterpret_cast<const float4 *>(&my_rn[g4 * 8 + hh * 4]);
-                acc0[g4 * 4 + 0] = acc1[g4 * 4 + 0] = v.x;
-                acc0[g4 * 4 + 1] = acc1[g4 * 4 + 1] = v.y;
-                acc0[g4 * 4 + 2] = acc1[g4 * 4 + 2] = v.z;
-                acc0[g4 * 4 + 3] = acc1[g4 * 4 + 3] = v.w;
+            // the accumulators start at the row norms: one more product, of
+            // the norm split into three BF16 parts (their sum is the FP32
+            // norm exactly) against ones, so the norms never leave their own
+            // lanes (rows past the tile: +inf)
+            const float nr = vr ? rn : kInf;
+            const __bf16 n0 = (__bf16)nr;
+            const float r1 = vr ? rn - float(n0) : 0.f;
+            const __bf16 n1 = (__bf16)r1;
+            const __bf16 n2 = (__bf16)(r1 - float(n1));
+            bf16x8_t an = {}, ones = {};
+            if (hh == 0) {
+                an[0] = n0;
+                an[1] = n1;
+                an[2] = n2;
+                ones[0] = ones[1] = ones[2] = (__bf16)1.0f;
             }
+            const f32x16_t zero = {};
+            const f32x16_t accn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an, ones, zero, 0, 0, 0);
+            f32x16_t acc0 = accn, acc1 = accn;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[s], bq0[s], acc0, 0, 0, 0);
