@@ -507,7 +507,7 @@ __device__ __forceinline__ void search_valu_body(const SearchArgs &a) {
                     ++n_pass;
                     if (cand) {
                         float x = sd[c];
-                        if (RESCORE) x = (float)d2_fp64<D>(q, rp + (t0 + c) * DP);
+                        if (RESCORE) x = (float)d2_fp64<D, true>(q, rp + (t0 + c) * DP);
                         if (x < dist[K - 1]) {
                             insert(x, base + t0 + c);
                             ++n_ins;
