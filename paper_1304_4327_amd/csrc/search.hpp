@@ -54,7 +54,7 @@ struct SearchArgs {
                                 // seed adds its second pass's counts to the next
                                 // ST_COUNT
     uint32_t *wave_log;         // debug: 8 words per wave (ticks, scores, tiles, inserts, passes, leaf,
-                                // staged tiles and filter candidates of the d = 64 sweep)
+                                // staged tiles of the d = 64 sweep, candidates of the BF16 filters)
     // Score log of the debug kernel (launch_search_valu_debug_d3): one
     // record of kDbgWords words per Score call, or NULL; and the visit order
     // (0: nearer child first, 1: farther child first)

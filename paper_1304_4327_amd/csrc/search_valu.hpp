@@ -225,6 +225,7 @@ __device__ __forceinline__ void search_valu_body(const SearchArgs &a) {
     }
     float bound2 = (!SEEDED || a.bound == KNN_BOUND_NONE) ? kInf : seed2;
     uint32_t n_score = 0, n_tiles = 0, n_ins = 0, n_pass = 0;
+    [[maybe_unused]] uint32_t n_cand = 0;  // MT: rows passing the BF16 filter
     uint64_t n_pairs = 0;
     int n_valid = __popcll(ballot(valid));
 
@@ -448,6 +449,7 @@ __device__ __forceinline__ void search_valu_body(const SearchArgs &a) {
                 mask |= (__float_as_uint(oth - thr) >> 31) << (16 + r);
             }
             if (!ballot(mask != 0)) return;  // lists unchanged, and so the bound
+            n_cand += __popc(mask);
             // survivors: one per lane per round, FP64 re-score, insert (a lane
             // without one re-scores row 0 and inserts +inf, a no-op)
 #pragma unroll 1
@@ -686,11 +688,12 @@ __device__ __forceinline__ void search_valu_body(const SearchArgs &a) {
         if (SEEDED && a.fallback && fb_leaf) a.fallback[qleaf] = 1;
     }
     if (a.wave_log || a.stats) {
-        int ins = n_ins, ins1 = second ? s_ins : n_ins;
+        int ins = n_ins, ins1 = second ? s_ins : n_ins, cand = int(n_cand);
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             ins += __shfl_xor(ins, off);
             if constexpr (SEEDED) ins1 += __shfl_xor(ins1, off);
+            if constexpr (MT) cand += __shfl_xor(cand, off);
         }
         if (a.wave_log && lane == 0) {
             uint32_t *w = a.wave_log + int64_t(wave) * 8;
@@ -701,6 +704,7 @@ __device__ __forceinline__ void search_valu_body(const SearchArgs &a) {
             w[3] = uint32_t(ins);
             w[4] = n_pass;
             w[5] = uint32_t(qleaf);
+            if constexpr (MT) w[7] = uint32_t(cand);
         }
         if constexpr (SEEDED) {
             const uint64_t fbmask = ballot(fb_q);
