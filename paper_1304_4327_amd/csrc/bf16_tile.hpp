@@ -94,6 +94,68 @@ __device__ __forceinline__ float bf16_ref_operand(const float *rrow, const float
     return rn;
 }
 
+// The same two operands with the centre held in registers: tc[8 s + e] is
+// the centre at dimension 16 s + 8 h + e of this lane's half h.
+template <int DP>
+__device__ __forceinline__ float bf16_query_operand_r(const float *qrow, const float (&tc)[DP / 2], int h,
+                                                      bool valid, bf16x8_t (&bq)[DP / 16]) {
+    float qn = 0.f;
+#pragma unroll
+    for (int s = 0; s < DP / 16; ++s) {
+        const float4 *xp = reinterpret_cast<const float4 *>(qrow + s * 16 + h * 8);
+        const float4 x0 = xp[0], x1 = xp[1];
+        const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float qd = valid ? xv[e] - tc[s * 8 + e] : 0.f;
+            qn = fmaf(qd, qd, qn);
+            bq[s][e] = (__bf16)(-2.0f * qd);
+        }
+    }
+    return qn;
+}
+template <int DP>
+__device__ __forceinline__ float bf16_ref_operand_r(const float *rrow, const float (&tc)[DP / 2], int h,
+                                                    bool valid, bf16x8_t (&ar)[DP / 16]) {
+    float rn = 0.f;
+#pragma unroll
+    for (int s = 0; s < DP / 16; ++s) {
+        const float4 *src = reinterpret_cast<const float4 *>(rrow + s * 16 + h * 8);
+        const float4 v0 = src[0], v1 = src[1];
+        const float rv[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float rd = valid ? rv[e] - tc[s * 8 + e] : 0.f;
+            rn = fmaf(rd, rd, rn);
+            ar[s][e] = (__bf16)rd;
+        }
+    }
+    return rn;
+}
+
+// The accumulators' initial values ||r_i'||^2 without leaving the lanes: a
+// product of each row's norm split into three BF16 parts (their sum is the
+// FP32 norm exactly: 3 x 8 significand bits) against ones.  rn is the full
+// norm of row lane % 32 (+inf for rows past the tile: then the other parts
+// are 0 and no product is 0 x inf); the result's register r of lane l holds
+// the norm of row 8(r/4) + 4h + r%4, as the tile product expects.
+__device__ __forceinline__ f32x16_t bf16_norm_init(float rn, bool vr, int h) {
+    const float nr = vr ? rn : __builtin_inff();
+    const __bf16 n0 = (__bf16)nr;
+    const float r1 = vr ? rn - float(n0) : 0.f;
+    const __bf16 n1 = (__bf16)r1;
+    const __bf16 n2 = (__bf16)(r1 - float(n1));
+    bf16x8_t an = {}, ones = {};
+    if (h == 0) {
+        an[0] = n0;
+        an[1] = n1;
+        an[2] = n2;
+        ones[0] = ones[1] = ones[2] = (__bf16)1.0f;
+    }
+    const f32x16_t zero = {};
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(an, ones, zero, 0, 0, 0);
+}
+
 // Largest |r'| of a tile from each lane's full row norm rn (rows past the
 // tile invalid): a DPP maximum over each 16 rows, then the two halves on the
 // scalar unit (non-negative floats order as unsigned integers); hardware

@@ -35,11 +35,11 @@
 
 namespace knnx {
 
-// dynamic LDS per wave: the leaf centre (DP floats), the tile's row norms
-// (32 floats) and, at write-out, both half-lists (64 lanes x K keys + indices)
+// dynamic LDS per wave: both half-lists at write-out (64 lanes x K keys +
+// indices); the walk and the tiles use none
 template <int DP, int K>
 constexpr size_t mfma_lds_per_wave() {
-    return size_t(DP) * 4 + 32 * 4 + size_t(64) * K * 8;
+    return size_t(64) * K * 8;
 }
 
 template <int DP>
@@ -94,9 +94,7 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
 
     extern __shared__ __align__(16) char smem[];
     char *wbase = smem + size_t(wslot) * mfma_lds_per_wave<DP, K>();
-    float *s_cen = reinterpret_cast<float *>(wbase);
-    float *s_rn = s_cen + DP;
-    float *s_key = s_rn + 32;                               // [64][K]
+    float *s_key = reinterpret_cast<float *>(wbase);        // [64][K]
     int *s_ord = reinterpret_cast<int *>(s_key + 64 * K);   // [64][K]
     auto wave_sync = [] {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -104,16 +102,25 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
 
-    // leaf centre, query operand -2 (q - c) in BF16, |q - c|^2 in FP32
-    if (lane < DP) s_cen[lane] = 0.5f * (qb[lane] + qb[DP + lane]);
-    wave_sync();
-    bf16x8_t bq[S];
-    float qn = bf16_query_operand<DP>(a.qpts + int64_t(qpos) * DP, s_cen, h, valid, bq);
-    qn = xor32_op(qn, OpAdd());
-    const float qlen = sqrtf(qn);
     // leaf box for Score: lane l holds dimension l (0 beyond d, as stored)
     const float qlo = lane < DP ? qb[lane] : 0.f;
     const float qhi = lane < DP ? qb[DP + lane] : 0.f;
+    // leaf centre in registers (this lane's operand dimensions), query
+    // operand -2 (q - c) in BF16, |q - c|^2 in FP32.  Nothing here or in the
+    // tiles goes through LDS with a fence: a fence ahead of the walk would
+    // turn its wave-uniform box loads into vector loads.
+    float tc[S * 8];
+    {
+        const float cl = 0.5f * (qlo + qhi);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) tc[s * 8 + e] = __shfl(cl, s * 16 + h * 8 + e);
+    }
+    bf16x8_t bq[S];
+    float qn = bf16_query_operand_r<DP>(a.qpts + int64_t(qpos) * DP, tc, h, valid, bq);
+    qn = xor32_op(qn, OpAdd());
+    const float qlen = sqrtf(qn);
     const float lam2 = 2.0f * a.qlam[qnode];
     const float seed = a.seed ? fmaxf(a.seed[qleaf], 0.0f) : kInf;
     const float seed2 = seed * seed;
@@ -189,22 +196,11 @@ __global__ __launch_bounds__(256) void k_search_mfma(const SearchArgs a) {
         const int islot = vr ? i : 0;  // rows past the leaf read slot 0 (in bounds)
         // reference operand: (r - c) in BF16, |r - c|^2 in FP32
         bf16x8_t ar[S];
-        float rn = bf16_ref_operand<DP>(rp + islot * DP, s_cen, h, vr, ar);
+        float rn = bf16_ref_operand_r<DP>(rp + islot * DP, tc, h, vr, ar);
         rn = xor32_op(rn, OpAdd());
         const float rlen = bf16_tile_rlen(rn, vr);  // largest |r'| of the tile
-        if (h == 0) s_rn[i] = vr ? rn : kInf;
-        wave_sync();
-        f32x16_t acc;
-#pragma unroll
-        for (int g4 = 0; g4 < 4; ++g4) {
-            const float4 v = *reinterpret_cast<const float4 *>(&s_rn[g4 * 8 + h * 4]);
-            acc[g4 * 4 + 0] = v.x;
-            acc[g4 * 4 + 1] = v.y;
-            acc[g4 * 4 + 2] = v.z;
-            acc[g4 * 4 + 3] = v.w;
-        }
-        acc = bf16_tile_product<DP>(ar, bq, acc);
-        wave_sync();  // s_rn is rewritten by the next tile
+        // accumulators start at the row norms (one more product, in lane)
+        f32x16_t acc = bf16_tile_product<DP>(ar, bq, bf16_norm_init(rn, vr, h));
         // keep D < T - |q'|^2 + M (the margin is 1.25 times the proven
         // bound, so the strict test keeps every row the bound admits); T is
         // capped at FLT_MAX: rows past the leaf hold +inf and never pass,

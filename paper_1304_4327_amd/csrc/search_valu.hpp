@@ -407,24 +407,9 @@ __device__ __forceinline__ void search_valu_body(const SearchArgs &a) {
             // the margin only needs an upper bound)
             const float rlen =
                 __builtin_amdgcn_sqrtf(uniform_f(reduce32(vr ? rn : 0.f, OpMax()))) * (1.0f + 0x1p-20f);
-            // the accumulators start at the row norms: one more product, of
-            // the norm split into three BF16 parts (their sum is the FP32
-            // norm exactly) against ones, so the norms never leave their own
-            // lanes (rows past the tile: +inf)
-            const float nr = vr ? rn : kInf;
-            const __bf16 n0 = (__bf16)nr;
-            const float r1 = vr ? rn - float(n0) : 0.f;
-            const __bf16 n1 = (__bf16)r1;
-            const __bf16 n2 = (__bf16)(r1 - float(n1));
-            bf16x8_t an = {}, ones = {};
-            if (hh == 0) {
-                an[0] = n0;
-                an[1] = n1;
-                an[2] = n2;
-                ones[0] = ones[1] = ones[2] = (__bf16)1.0f;
-            }
-            const f32x16_t zero = {};
-            const f32x16_t accn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an, ones, zero, 0, 0, 0);
+            // the accumulators start at the row norms, from one more product
+            // (the norms never leave their lanes: no LDS, no fence)
+            const f32x16_t accn = bf16_norm_init(rn, vr, hh);
             f32x16_t acc0 = accn, acc1 = accn;
 #pragma unroll
             for (int s = 0; s < S; ++s) {

@@ -153,6 +153,27 @@ def test_any_seed_gives_the_oracle_answer(kind, name, precision, scale):
         assert 0 < st["fallback_leaves"] < nl
 
 
+@pytest.mark.parametrize("kind", ["zero", "half", "random"])
+def test_any_seed_per_leaf_bf16_kernel(kind):
+    """Stride 32 with lists of 32: the per-leaf BF16 kernel and its second
+    launch over the flagged leaves give the oracle's answer for any seed."""
+    rng = np.random.default_rng(24)
+    basis = rng.standard_normal((6, 24))
+    ref = (rng.random((12000, 6)) @ basis + 0.05 * rng.standard_normal((12000, 24))).astype(np.float32)
+    q = (rng.random((1500, 6)) @ basis + 0.05 * rng.standard_normal((1500, 24))).astype(np.float32)
+    k, leaf = 20, 32
+    plain = _seeded(ref, q, k, leaf, lambda n: None, "bf16")
+    got = _seeded(ref, q, k, leaf, _seed_fn(kind, plain[1]), "bf16")
+    oi, od = ok.knn(q, ref, k)
+    parity.assert_ok(q, ref, k, got[0], got[1], oi, od)
+    assert np.array_equal(got[0], plain[0]) and np.array_equal(got[1], plain[1])
+    st, nl = got[2], got[2]["n_query_leaves"]
+    if kind == "zero":
+        assert st["fallback_leaves"] == nl
+    elif kind == "half":
+        assert st["fallback_leaves"] == nl // 2
+
+
 def test_trained_seed_prunes_more_and_stays_exact():
     """Train on 8 seeded draws of the Zipf-GMM workload (scaled down), then
     on a held-out draw: the seeded search returns the oracle's answer with
