@@ -545,8 +545,10 @@ k_search_mfma_sweep(const SearchArgs a) {
             v[e + 1] = x.y;
         }
     };
-    // a kept leaf: the barrier publishes the tile staged last, then this leaf
-    // is staged into the other buffer and the tile staged last multiplied.
+    // a kept leaf: the barrier publishes the tile staged last, which is then
+    // multiplied (its LDS reads queue behind no staging writes, and this
+    // leaf's loads get that much longer to land), then this leaf is staged
+    // into the other buffer.
     // Every wave takes the same steps (the block's union mask is the same in
     // all of them), so the barriers match.  Safety of the two buffers: a
     // wave stages into the buffer of the tile before last, and every wave
@@ -559,8 +561,8 @@ k_search_mfma_sweep(const SearchArgs a) {
         ++n_staged;
         const int b = pend_b ^ 1;
         const int cnt = uniform_i(rr.y);
-        stage(b, cnt, v);
         if (pending) compute(pend_b, pend_base, pend_cnt, pend_own);
+        stage(b, cnt, v);
         pending = true;
         pend_b = b;
         pend_base = uniform_i(rr.x);
