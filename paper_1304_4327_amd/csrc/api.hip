@@ -292,6 +292,32 @@ knn_status search(const knn_tree *ref, const knn_tree *query, int k, const knn_o
     } else if (dstats) {
         KNN_HIP(zero_words(dstats, 2 * 2 * ST_COUNT, s));
     }
+    // the d = 64 sweep's wave-independent form: its reference-side operands,
+    // made once per search (not in the no-alloc form, which keeps the staged
+    // sweep: they take 4 KB per reference leaf)
+    if (bf16 && ref->dp == 64 && !arena && !dbg) {
+        const int nl = int(ref->first_leaf) + 1;
+        const size_t pl = size_t((nl + kSweepBlock - 1) / kSweepBlock) * kSweepBlock;  // padded leaves
+        uint16_t *abf = nullptr, *cbf = nullptr;
+        float *rn = nullptr, *rlen = nullptr, *cn = nullptr, *lam = nullptr, *bcen = nullptr, *rcb = nullptr;
+        KNN_HIP(sc.get(&abf, pl * 32 * 64));
+        KNN_HIP(sc.get(&rn, pl * 32));
+        KNN_HIP(sc.get(&rlen, pl));
+        KNN_HIP(sc.get(&cbf, pl * 64));
+        KNN_HIP(sc.get(&cn, pl));
+        KNN_HIP(sc.get(&lam, pl));
+        KNN_HIP(sc.get(&bcen, pl / kSweepBlock * 64));
+        KNN_HIP(sc.get(&rcb, pl / kSweepBlock));
+        KNN_HIP(launch_wsweep_prep(a, abf, rn, rlen, cbf, cn, lam, bcen, rcb, s));
+        a.sw_abf = abf;
+        a.sw_rn = rn;
+        a.sw_rlen = rlen;
+        a.sw_cbf = cbf;
+        a.sw_cn = cn;
+        a.sw_lam = lam;
+        a.sw_bcen = bcen;
+        a.sw_rcb = rcb;
+    }
     // device timing (not in the no-alloc form: it creates no events)
     hipEvent_t ev[4] = {};
     struct EvGuard {

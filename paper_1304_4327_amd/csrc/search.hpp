@@ -53,6 +53,19 @@ struct SearchArgs {
     unsigned long long *stats;  // ST_COUNT counters, or NULL; the FP32 kernel with a
                                 // seed adds its second pass's counts to the next
                                 // ST_COUNT
+    // wave-independent d = 64 sweep (k_search_mfma_sweep with W): the
+    // reference side of every tile and block Score, centred on the centre
+    // C_B of the leaf's block (subtree of 32 leaves), made once per search
+    // by k_wsweep_prep; sw_abf == NULL selects the staged sweep.  Leaves are
+    // padded to whole blocks.
+    const uint16_t *sw_abf;  // [leaf][32 rows][h][s][8] bf16(-2 (r - C_B)), 0 past the leaf
+    const float *sw_rn;      // [leaf][32] |r - C_B|^2 (FP32), +inf past the leaf
+    const float *sw_rlen;    // [leaf] largest |r - C_B|, rounded up
+    const uint16_t *sw_cbf;  // [leaf][h][s][8] bf16(-2 (C_L - C_B)), C_L the leaf's box centre
+    const float *sw_cn;      // [leaf] |C_L - C_B|^2, +inf for empty or padding leaves
+    const float *sw_lam;     // [leaf] lambda of the leaf, 0 for padding
+    const float *sw_bcen;    // [block][DP] C_B
+    const float *sw_rcb;     // [block] largest |C_L - C_B| of the block, rounded up
     uint32_t *wave_log;         // debug: 8 words per wave (ticks, scores, tiles, inserts, passes, leaf,
                                 // staged tiles of the d = 64 sweep, candidates of the BF16 filters)
     // Score log of the debug kernel (launch_search_valu_debug_d3): one
@@ -109,6 +122,16 @@ hipError_t launch_search_valu_debug_d3(const SearchArgs &a, int K, int grid, hip
 // when a.seed is set
 hipError_t launch_search_mt_d16(const SearchArgs &a, int K, int grid, hipStream_t s);
 hipError_t launch_search_mt_d32(const SearchArgs &a, int K, int grid, hipStream_t s);
+
+// reference leaves the d = 64 sweep scores together (one subtree)
+constexpr int kSweepBlock = 32;
+
+// reference-side operands of the wave-independent d = 64 sweep (see the
+// sw_* fields): fills them for the n_blocks * 32 (padded) leaves of the
+// reference tree in args
+hipError_t launch_wsweep_prep(const SearchArgs &args, uint16_t *abf, float *rn, float *rlen,
+                              uint16_t *cbf, float *cn, float *lam, float *bcen, float *rcb,
+                              hipStream_t s);
 
 // BF16 MFMA kernels (search_mfma_d*.hip), stride 16, 32 or 64
 hipError_t launch_search_mfma_dp16(const SearchArgs &a, int K, int grid, hipStream_t s);

@@ -49,7 +49,6 @@
 namespace knnx {
 
 constexpr int kWgLeaves = 4;   // query leaves (one per wave) per workgroup
-constexpr int kSweepBlock = 32;  // reference leaves scored together
 
 // LDS layout of one workgroup
 template <int DP, int K>
@@ -91,7 +90,7 @@ constexpr int kMiscQlen = 24;     // [kWgLeaves] largest |q - c| of each wave
 // tile's latency chain (staging barrier, dependent MFMAs, LDS reads) is then
 // covered by the other workgroup.  For K <= 50 this fits 256 registers;
 // larger lists keep one workgroup.
-template <int DP, int K>
+template <int DP, int K, bool W = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 50 ? 2 : 1))) void
 k_search_mfma_sweep(const SearchArgs a) {
     static_assert(DP % 16 == 0, "MFMA tiles need the stride to be a multiple of 16");
@@ -571,66 +570,270 @@ k_search_mfma_sweep(const SearchArgs a) {
     };
 
     const int n_steps = use_sort ? n_blocks : bsteps;
-    for (int st = 0; st < n_steps; ++st) {
-        int rb;
-        if (use_sort) {
-            rb = uniform_i(int(s_order[st]));
-        } else {
-            const int off = (st + 1) >> 1;
-            rb = (st & 1) ? sblock + off : sblock - off;
-            if (rb < 0 || rb >= n_blocks) continue;  // uniform
-        }
-        stage_centres(rb);
-        lds_barrier();
-        take_bounds();
-        if (use_sort) {
-            // every query's bound is at most the largest wave bound B (idle
-            // waves publish -inf); the keys are ascending, so when this
-            // block is out of reach, all later ones are too
-            float bw = -kInf;
-#pragma unroll
-            for (int g = 0; g < kWgLeaves; ++g) bw = fmaxf(bw, s_misc[kMiscBound + g]);
-            const float bmax = bw < kInf ? __builtin_amdgcn_sqrtf(fmaxf(bw, 0.f)) * (1.0f + 0x1p-20f) : kInf;
-            if (uniform_f(s_okey[st]) > (bmax + R) * kSlack) break;
-        }
-        const uint32_t own = block_mask();
-        n_score += __popc(uint32_t(ballot(lane < 32 && s_cn[lane & 31] < kInf)));
-        if (lane == 0) s_mask[w] = own;
-        lds_barrier();
-        uint32_t uni = 0;
-#pragma unroll
-        for (int g = 0; g < kWgLeaves; ++g) uni |= s_mask[g];
-        uni = uint32_t(uniform_i(int(uni)));
-        if (!uni) continue;
-        // two register sets used in turn: a leaf's loads land in the set that
-        // the next visit reads, so they stay in flight while the current leaf
-        // is processed (no register copy forces an early wait)
-        int2 rr_a = make_int2(0, 0), rr_b = make_int2(0, 0);
-        float v_a[E], v_b[E];
-        int ca = __builtin_ctz(uni);
-        uni &= uni - 1u;
-        fetch(rb * NB + ca, rr_a, v_a);
-        for (;;) {
-            // past the last kept leaf the fetch repeats the current one (in
-            // bounds, never visited): the loads stay unconditional
-            const int cb = uni ? __builtin_ctz(uni) : ca;
-            const bool more_b = uni != 0;
+    if constexpr (!W) {
+        const int n_steps = use_sort ? n_blocks : bsteps;
+        for (int st = 0; st < n_steps; ++st) {
+            int rb;
+            if (use_sort) {
+                rb = uniform_i(int(s_order[st]));
+            } else {
+                const int off = (st + 1) >> 1;
+                rb = (st & 1) ? sblock + off : sblock - off;
+                if (rb < 0 || rb >= n_blocks) continue;  // uniform
+            }
+            stage_centres(rb);
+            lds_barrier();
+            take_bounds();
+            if (use_sort) {
+                // every query's bound is at most the largest wave bound B (idle
+                // waves publish -inf); the keys are ascending, so when this
+                // block is out of reach, all later ones are too
+                float bw = -kInf;
+    #pragma unroll
+                for (int g = 0; g < kWgLeaves; ++g) bw = fmaxf(bw, s_misc[kMiscBound + g]);
+                const float bmax = bw < kInf ? __builtin_amdgcn_sqrtf(fmaxf(bw, 0.f)) * (1.0f + 0x1p-20f) : kInf;
+                if (uniform_f(s_okey[st]) > (bmax + R) * kSlack) break;
+            }
+            const uint32_t own = block_mask();
+            n_score += __popc(uint32_t(ballot(lane < 32 && s_cn[lane & 31] < kInf)));
+            if (lane == 0) s_mask[w] = own;
+            lds_barrier();
+            uint32_t uni = 0;
+    #pragma unroll
+            for (int g = 0; g < kWgLeaves; ++g) uni |= s_mask[g];
+            uni = uint32_t(uniform_i(int(uni)));
+            if (!uni) continue;
+            // two register sets used in turn: a leaf's loads land in the set that
+            // the next visit reads, so they stay in flight while the current leaf
+            // is processed (no register copy forces an early wait)
+            int2 rr_a = make_int2(0, 0), rr_b = make_int2(0, 0);
+            float v_a[E], v_b[E];
+            int ca = __builtin_ctz(uni);
             uni &= uni - 1u;
-            fetch(rb * NB + cb, rr_b, v_b);
-            visit(rr_a, v_a, (own >> ca) & 1u);
-            if (!more_b) break;
-            const int cc = uni ? __builtin_ctz(uni) : cb;
-            const bool more_c = uni != 0;
-            uni &= uni - 1u;
-            fetch(rb * NB + cc, rr_a, v_a);
-            visit(rr_b, v_b, (own >> cb) & 1u);
-            if (!more_c) break;
-            ca = cc;
+            fetch(rb * NB + ca, rr_a, v_a);
+            for (;;) {
+                // past the last kept leaf the fetch repeats the current one (in
+                // bounds, never visited): the loads stay unconditional
+                const int cb = uni ? __builtin_ctz(uni) : ca;
+                const bool more_b = uni != 0;
+                uni &= uni - 1u;
+                fetch(rb * NB + cb, rr_b, v_b);
+                visit(rr_a, v_a, (own >> ca) & 1u);
+                if (!more_b) break;
+                const int cc = uni ? __builtin_ctz(uni) : cb;
+                const bool more_c = uni != 0;
+                uni &= uni - 1u;
+                fetch(rb * NB + cc, rr_a, v_a);
+                visit(rr_b, v_b, (own >> cb) & 1u);
+                if (!more_c) break;
+                ca = cc;
+            }
         }
-    }
-    if (pending) {
-        lds_barrier();
-        compute(pend_b, pend_base, pend_cnt, pend_own);
+        if (pending) {
+            lds_barrier();
+            compute(pend_b, pend_base, pend_cnt, pend_own);
+        }
+    } else {
+        // ---- wave-independent sweep: no barrier per leaf -------------------
+        // Each wave scores the blocks against its own queries and multiplies
+        // its own kept leaves, reading the reference side made by
+        // k_wsweep_prep: per block, the query operand q - C_B (BF16) and
+        // |q - C_B|^2 (FP32) serve the block Score and every tile of the
+        // block.  The waves share only the block order and, through relaxed
+        // LDS words, their smallest k-th distances for the B(Par) term (an
+        // older value is a larger one: still a bound).
+        uint32_t *s_lo = reinterpret_cast<uint32_t *>(s_misc + kMiscBound + kWgLeaves);
+        auto publish = [&]() {
+            if (lane == 0)
+                __hip_atomic_store(&s_lo[w], __float_as_uint(lo_k), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        };
+        auto par_bound = [&]() {
+            if (a.bound != KNN_BOUND_B || !(lam2_anc < kInf)) return;
+            float lo_all = kInf;
+#pragma unroll
+            for (int g = 0; g < kWgLeaves; ++g)
+                lo_all = fminf(lo_all, __uint_as_float(__hip_atomic_load(&s_lo[g], __ATOMIC_RELAXED,
+                                                                         __HIP_MEMORY_SCOPE_WORKGROUP)));
+            if (lo_all < kInf) {
+                const float t = __builtin_amdgcn_sqrtf(lo_all) + lam2_anc;
+                bound2 = uniform_f(fminf(bound2, t * t));
+            }
+        };
+        const __bf16 *abf = reinterpret_cast<const __bf16 *>(a.sw_abf);
+        const __bf16 *cbf = reinterpret_cast<const __bf16 *>(a.sw_cbf);
+        if (lane == 0) s_lo[w] = __float_as_uint(kInf);
+        __syncthreads();
+        for (int st = 0; st < n_steps && has_leaf; ++st) {
+            int rb;
+            if (use_sort) {
+                rb = uniform_i(int(s_order[st]));
+            } else {
+                const int off = (st + 1) >> 1;
+                rb = (st & 1) ? sblock + off : sblock - off;
+                if (rb < 0 || rb >= n_blocks) continue;  // uniform
+            }
+            par_bound();
+            if (use_sort) {
+                // no query of this wave needs a block whose key exceeds its
+                // bound plus R; the keys ascend
+                const float lim = valid ? fminf(pair_kth, bound2) : -kInf;
+                const float bw = uniform_f(reduce64(lim, OpMax()));
+                const float bmax =
+                    bw < kInf ? __builtin_amdgcn_sqrtf(fmaxf(bw, 0.f)) * (1.0f + 0x1p-20f) : kInf;
+                if (uniform_f(s_okey[st]) > (bmax + R) * kSlack) break;
+            }
+            // query operand of the block: q - C_B at this lane's dimensions
+            const float *cb = a.sw_bcen + int64_t(rb) * DP;
+            bf16x8_t bqb[S];
+            float qnb = 0.f;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const float4 c0 = *reinterpret_cast<const float4 *>(cb + s * 16 + h * 8);
+                const float4 c1 = *reinterpret_cast<const float4 *>(cb + s * 16 + h * 8 + 4);
+                const float4 x0 = *reinterpret_cast<const float4 *>(my_q + s * 16 + h * 8);
+                const float4 x1 = *reinterpret_cast<const float4 *>(my_q + s * 16 + h * 8 + 4);
+                const float dv[8] = {x0.x - c0.x, x0.y - c0.y, x0.z - c0.z, x0.w - c0.w,
+                                     x1.x - c1.x, x1.y - c1.y, x1.z - c1.z, x1.w - c1.w};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    qnb = fmaf(dv[e], dv[e], qnb);
+                    bqb[s][e] = (__bf16)dv[e];
+                }
+            }
+            qnb += __shfl_xor(qnb, 32);  // the query's whole |q - C_B|^2
+            const float qlenb = sqrtf(qnb);
+            // block Score: rows = the block's 32 leaves, value |C_L - C_B|^2
+            // - 2 (q - C_B).(C_L - C_B); keep (p, L) unless the low end of
+            // |p - C_L|^2 exceeds (b_p + lambda_L)^2
+            const int L0 = rb * NB;
+            uint32_t own;
+            {
+                f32x16_t acc;
+                float lam[16];
+#pragma unroll
+                for (int g4 = 0; g4 < 4; ++g4) {
+                    const float4 v = *reinterpret_cast<const float4 *>(a.sw_cn + L0 + g4 * 8 + h * 4);
+                    const float4 l = *reinterpret_cast<const float4 *>(a.sw_lam + L0 + g4 * 8 + h * 4);
+                    acc[g4 * 4 + 0] = v.x;
+                    acc[g4 * 4 + 1] = v.y;
+                    acc[g4 * 4 + 2] = v.z;
+                    acc[g4 * 4 + 3] = v.w;
+                    lam[g4 * 4 + 0] = l.x;
+                    lam[g4 * 4 + 1] = l.y;
+                    lam[g4 * 4 + 2] = l.z;
+                    lam[g4 * 4 + 3] = l.w;
+                }
+                const __bf16 *arow = cbf + int64_t(L0 + j) * DP + h * (DP / 2);
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const bf16x8_t ar = *reinterpret_cast<const bf16x8_t *>(arow + s * 8);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, bqb[s], acc, 0, 0, 0);
+                }
+                const float low0 = qnb - bf16_margin<DP>(qlenb, uniform_f(a.sw_rcb[rb]));
+                const float lim = fminf(pair_kth, bound2);
+                const float bp =
+                    lim < kInf ? __builtin_amdgcn_sqrtf(fmaxf(lim, 0.f)) * (1.0f + 0x1p-20f) : kInf;
+                uint32_t m16 = 0;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float t = bp + lam[r];
+                    m16 |= ((~__float_as_uint(t * t * kSlack - (acc[r] + low0))) >> 31) << r;
+                }
+                uint32_t m =
+                    (m16 & 0xfu) | ((m16 & 0xf0u) << 4) | ((m16 & 0xf00u) << 8) | ((m16 & 0xf000u) << 12);
+                m <<= 4 * h;
+                m = !valid ? 0u : a.bound == KNN_BOUND_NONE ? 0xffffffffu : m;
+                float mf = reduce64(__builtin_bit_cast(float, m), OpOrBits());
+                const uint32_t vrows = uint32_t(ballot(lane < 32 && a.sw_cn[L0 + j] < kInf));
+                own = uint32_t(uniform_i(__builtin_bit_cast(int, mf))) & vrows;
+                n_score += __popc(vrows);
+            }
+            // tiles of the kept leaves, software-pipelined: the next kept
+            // leaf's operand rows, row norm, range and |r - C_B| bound are
+            // loaded while the current one is multiplied (two register sets
+            // in turn; past the last leaf the loads repeat the current one)
+            struct TileIn {
+                bf16x8_t ar[S];
+                float rnj;  // |r_j - C_B|^2 of row j = lane % 32
+                int2 rr;
+                float rl;
+            };
+            auto tload = [&](int leaf, TileIn &t) {
+                const __bf16 *arow = abf + (int64_t(leaf) * NB + j) * DP + h * (DP / 2);
+#pragma unroll
+                for (int s = 0; s < S; ++s) t.ar[s] = *reinterpret_cast<const bf16x8_t *>(arow + s * 8);
+                t.rnj = a.sw_rn[int64_t(leaf) * NB + j];
+                t.rr = a.rrange[a.r_first_leaf + leaf];
+                t.rl = a.sw_rlen[leaf];
+            };
+            auto tile = [&](int leaf, const TileIn &t) {
+                const int base = uniform_i(t.rr.x);
+                const int cnt = uniform_i(t.rr.y);
+                ++n_tiles;
+                n_pairs += uint64_t(cnt) * uint64_t(qcount);
+                // accumulators from the split-norm product (rows past the
+                // leaf: +inf), then the k-steps
+                f32x16_t acc = bf16_norm_init(t.rnj, t.rnj < kInf, h);
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(t.ar[s], bqb[s], acc, 0, 0, 0);
+                // keep D < T - |q - C_B|^2 + M (strict: M is 1.25 times the
+                // proven bound); T capped at FLT_MAX, rows past the leaf +inf
+                const float marg = bf16_margin<DP>(qlenb, uniform_f(t.rl));
+                const float lim = fminf(pair_kth, bound2) * kSlack;
+                const float thr = valid ? fminf(lim - qnb + marg, 0x1.fffffep127f) : -kInf;
+                float amin = acc[0];
+#pragma unroll
+                for (int r = 1; r < 16; ++r) amin = fminf(amin, acc[r]);
+                if (!ballot(amin < thr)) return;
+                uint32_t mask = 0;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) mask |= (__float_as_uint(acc[r] - thr) >> 31) << r;
+                n_cand += __popc(mask);
+                const float *rows = a.rlpts + int64_t(leaf) * a.r_leaf_slots * DP;
+#pragma unroll
+                for (int pass = 0; pass < 16; ++pass) {
+                    const bool has = mask != 0;
+                    if (!ballot(has)) break;
+                    ++n_pass;
+                    const int r = has ? __builtin_ctz(mask) : 0;
+                    mask &= mask - 1u;
+                    const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+                    const float x0 = (float)d2_fp64_rows<DP>(my_q, rows + (has ? row : 0) * DP);
+                    const float x = has ? x0 : kInf;
+                    n_ins += (x < dist[K - 1]) ? 1u : 0u;
+                    insert(x, base + row);
+                }
+                refresh_bound();
+                publish();
+                par_bound();
+            };
+            if (own) {
+                auto next = [&](int prev, bool &more) -> int {
+                    more = own != 0;
+                    const int c = more ? __builtin_ctz(own) : prev;
+                    own &= own - 1u;
+                    return c;
+                };
+                TileIn t0, t1;
+                bool m1, m2;
+                int c0 = __builtin_ctz(own);
+                own &= own - 1u;
+                tload(L0 + c0, t0);
+                for (;;) {
+                    const int c1 = next(c0, m1);
+                    tload(L0 + c1, t1);
+                    tile(L0 + c0, t0);
+                    if (!m1) break;
+                    const int c2 = next(c1, m2);
+                    tload(L0 + c2, t0);
+                    tile(L0 + c1, t1);
+                    if (!m2) break;
+                    c0 = c2;
+                }
+            }
+        }
     }
 
     // ---- write-out: FP64 re-score, merge the two half-lists ------------------
@@ -721,12 +924,18 @@ k_search_mfma_sweep(const SearchArgs a) {
     }
 }
 
+// the wave-independent form when the reference-side operands are given
 template <int DP>
 hipError_t launch_search_mfma_sweep(const SearchArgs &a, int K, int grid, hipStream_t s) {
+    const bool wave_independent = a.sw_abf != nullptr;
+    if (wave_independent && DP != 64) return hipErrorInvalidValue;
     switch (K) {
-#define KNN_CASE(KK)                                         \
-    case KK:                                                 \
-        k_search_mfma_sweep<DP, KK><<<grid, 256, 0, s>>>(a); \
+#define KNN_CASE(KK)                                               \
+    case KK:                                                       \
+        if (wave_independent)                                      \
+            k_search_mfma_sweep<DP, KK, true><<<grid, 256, 0, s>>>(a); \
+        else                                                       \
+            k_search_mfma_sweep<DP, KK><<<grid, 256, 0, s>>>(a);   \
         break;
         KNN_CASE(4)
         KNN_CASE(5)

@@ -2,7 +2,10 @@
 knn_search, through the C ABI: the same answers and counters, bit for bit,
 on two calls in a row (the second with a smaller input, so stale scratch
 from the first call would show), for every kernel family and with a seed
-that sends leaves to the fallback pass; and the size limit."""
+that sends leaves to the fallback pass; and the size limit.  At d = 64 with
+BF16 tiles the no-alloc form runs the staged sweep (the wave-independent one
+needs 4 KB of operands per reference leaf): the answers and fallback counts
+are still identical, the traversal counters are not compared."""
 import numpy as np
 import pytest
 
@@ -54,7 +57,9 @@ def test_noalloc_matches_knn_search_twice(name, scales, precision, self_mode, se
                                      exclude_self=self_mode, seed_radius=seed, stats=True)
         torch.cuda.synchronize()
         assert torch.equal(got[0], want[0]) and torch.equal(got[1], want[1])
-        for key in ("score_calls", "pairs", "inserts", "fallback_leaves", "fallback_queries"):
+        same_kernel = not (precision == "bf16" and ref.shape[1] > 32)
+        keys = ("score_calls", "pairs", "inserts") if same_kernel else ()
+        for key in keys + ("fallback_leaves", "fallback_queries"):
             assert got[2][key] == want[2][key], key
         if seeded:
             assert got[2]["fallback_leaves"] > 0
