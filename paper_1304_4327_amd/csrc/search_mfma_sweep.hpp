@@ -423,7 +423,9 @@ k_search_mfma_sweep(const SearchArgs a) {
         for (int g = 0; g < kWgLeaves; ++g) rq = fmaxf(rq, s_misc[kMiscQlen + g]);
         // (|q - c| is an FP32 norm: a relative error of a few 1e-6, far inside
         // this rounding up)
-        R = uniform_f(rq) * (1.0f + 0x1p-12f);
+        // (the wave-independent form ends each wave's sweep on its own
+        // queries' bounds: their largest |q - c| is enough)
+        R = uniform_f(W ? ql : rq) * (1.0f + 0x1p-12f);
         __syncthreads();
     }
 
