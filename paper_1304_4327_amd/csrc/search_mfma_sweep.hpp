@@ -42,6 +42,18 @@
 // other buffer.  The waves exchange their bounds once per block: the query
 // node above the four leaves adds the B(Par) term, min over all its queries
 // of D_p[k] + 2 lambda(node).
+//
+// Wave-independent form (W, used whenever the reference-side operands of
+// k_wsweep_prep are given).  The staged form waits at one workgroup barrier
+// per kept leaf, for the slowest of four waves.  In the W form the four
+// waves share only the block order; each wave then, on its own, scores a
+// block's 32 leaves against its queries and multiplies its own kept leaves,
+// reading their operands from global memory with the next kept leaf's loads
+// in flight.  Everything is centred on the block's centre C_B: the reference
+// side (rows -2 (r - C_B) in BF16, their norms, leaf centres -2 (C_L - C_B))
+// is made once per search, and per block each wave forms q - C_B once for
+// the block Score and all of the block's tiles.  The margin is the same
+// bound with |q'| = |q - C_B| and the tile's largest |r - C_B|.
 #pragma once
 
 #include "search_mfma.hpp"
