@@ -585,7 +585,6 @@ k_search_mfma_sweep(const SearchArgs a) {
 
     const int n_steps = use_sort ? n_blocks : bsteps;
     if constexpr (!W) {
-        const int n_steps = use_sort ? n_blocks : bsteps;
         for (int st = 0; st < n_steps; ++st) {
             int rb;
             if (use_sort) {
