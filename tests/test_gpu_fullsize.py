@@ -93,3 +93,37 @@ def test_full_size_learned_sampled_rows(name, precision):
     print(f"fallback leaves {st['fallback_leaves']} of {st['n_query_leaves']}", flush=True)
     _every_row(gi, gd, len(ref))
     parity.assert_ok(q, ref, k, gi, gd, oi, od, rows=rows)
+
+
+def test_sweep_beyond_the_sorted_block_order():
+    """d = 64 with more reference blocks (32 leaves each) than the sweep
+    sorts per workgroup (2048): 2.2M reference points, 4096 blocks, visited
+    outward in tree order from the query centre's block without an early
+    end.  Both sweeps (the wave-independent one of knn_search, the staged
+    one of knn_search_noalloc) against the oracle on sampled rows."""
+    import torch
+    from paper_1304_4327_amd import knn
+    rng = np.random.default_rng(2048)
+    basis = rng.standard_normal((6, 64)).astype(np.float32)
+    ref = (rng.random((2_200_000, 6), dtype=np.float32) @ basis
+           + 0.05 * rng.standard_normal((2_200_000, 64), dtype=np.float32)).astype(np.float32)
+    q = (rng.random((3000, 6), dtype=np.float32) @ basis
+         + 0.05 * rng.standard_normal((3000, 64), dtype=np.float32)).astype(np.float32)
+    k, leaf = 10, 32
+    rows = np.sort(rng.choice(len(q), size=256, replace=False))
+    oi, od = ok.knn_rows(q, rows, ref, k)
+    print(f"many blocks: n_ref={len(ref)} n_q={len(q)} k={k}", flush=True)
+    rt = knn.knn_build_tree(torch.from_numpy(ref).cuda(), leaf)
+    qt = knn.knn_build_tree(torch.from_numpy(q).cuda(), leaf)
+    assert rt.info()["n_leaves"] // 32 > 2048
+    gi, gd, _ = knn.knn_search(rt, qt, k, precision="bf16")
+    out = (torch.empty((len(q), k), dtype=torch.int64, device="cuda"),
+           torch.empty((len(q), k), dtype=torch.float32, device="cuda"))
+    si, sd, _ = knn.knn_search_noalloc(rt, qt, k, out, precision="bf16")
+    torch.cuda.synchronize()
+    gi, gd, si, sd = gi.cpu().numpy(), gd.cpu().numpy(), si.cpu().numpy(), sd.cpu().numpy()
+    qt.close()
+    rt.close()
+    assert np.array_equal(gi, si) and np.array_equal(gd, sd)
+    _every_row(gi, gd, len(ref))
+    parity.assert_ok(q, ref, k, gi, gd, oi, od, rows=rows)
