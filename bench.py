@@ -384,7 +384,7 @@ def extras_cpu_baseline(ref, q, k, rows, far_ans, rng_ans, rng_lohi, kde_f, kde_
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
+        print(json.dumps({"error": "the library and this benchmark use one GPU only; "
                                    "--gpus must be 1 (no multi-GPU path)"}))
         sys.exit(2)
     if args.copy_calibration:

@@ -43,7 +43,7 @@ typedef enum knn_status {
     KNN_E_OOM = 3,         /* device allocation failed                      */
     KNN_E_DEVICE = 4,      /* HIP runtime error (no device, launch failure) */
     KNN_E_MODEL = 5,       /* seed-network file unreadable or inconsistent  */
-    KNN_E_UNSUPPORTED = 6  /* valid request this build does not implement   */
+    KNN_E_UNSUPPORTED = 6  /* valid request the library does not implement  */
 } knn_status;
 
 /* Pruning bound used by Score() (Section "k-Nearest Neighbor Search").
