@@ -22,6 +22,8 @@
 // FP64 accumulator.
 #pragma once
 
+#include <type_traits>
+
 #include "walk.hpp"
 
 namespace knnx {
@@ -119,20 +121,31 @@ __global__ __launch_bounds__(256) void k_kde(const KdeArgs a) {
         const float c2 = a.c * 1.44269504088896341f;
         float part = 0.f;
         // whole batches, no branch per pair: the slots past the leaf's points
-        // hold FLT_MAX, whose squared distance is +inf and kernel value 0
-        for (int t0 = 0; t0 < cnt; t0 += CH) {
+        // hold FLT_MAX, whose squared distance is +inf and kernel value 0.
+        // Only a leaf that holds one of the wave's own queries needs the
+        // per-pair test of the query's own slot.
+        auto batches = [&](auto skip_own) {
+            for (int t0 = 0; t0 < cnt; t0 += CH) {
 #pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                float sd = 0.f;
+                for (int c = 0; c < CH; ++c) {
+                    float sd = 0.f;
 #pragma unroll
-                for (int j = 0; j < DP; ++j) {
-                    const float df = q[j] - rp[(t0 + c) * DP + j];
-                    sd = fmaf(df, df, sd);
+                    for (int j = 0; j < DP; ++j) {
+                        const float df = q[j] - rp[(t0 + c) * DP + j];
+                        sd = fmaf(df, df, sd);
+                    }
+                    const float e = __builtin_amdgcn_exp2f(-sd * c2);
+                    if constexpr (decltype(skip_own)::value)
+                        part += (t0 + c == own) ? 0.f : e;
+                    else
+                        part += e;
                 }
-                const float e = __builtin_amdgcn_exp2f(-sd * c2);
-                part += (t0 + c == own) ? 0.f : e;
             }
-        }
+        };
+        if (ballot(own >= 0))
+            batches(std::true_type{});
+        else
+            batches(std::false_type{});
         if (valid) f += double(part);
     };
     tree_walk_once(a.r_first_leaf, score, leaf, [](float k0, float k1) { return k1 < k0; });
