@@ -7,78 +7,91 @@ namespace knnx {
 namespace {
 
 // One workgroup per block of 32 reference leaves (the subtree whose leaves
-// the sweep scores together); thread (li, i) = row i of leaf 32 rb + li.
+// the sweep scores together), four leaves at a time: thread t of a leaf's
+// 256 takes row t / 8, dimensions 8 (t % 8) .. + 7 (chunk c = 2 s + h of the
+// operand layout), so that reads and writes are whole 16-byte pieces.
 // Everything is centred on the block's box centre C_B = (lo + hi) / 2 of the
 // block's subtree node, the same FP32 value the search reads back from bcen.
-// The norms are FP32 sums of the FP32 differences (dimension order for rows,
-// a fixed lane tree for leaf centres): the tile margin counts that error.
+// Norms are FP32 sums of the FP32 differences in a fixed order (chunk, then
+// a lane tree): the tile margin counts that error.
 template <int DP>
 __global__ __launch_bounds__(1024) void k_wsweep_prep(const SearchArgs a, uint16_t *__restrict__ abf,
                                                       float *__restrict__ rn, float *__restrict__ rlen,
                                                       uint16_t *__restrict__ cbf, float *__restrict__ cn,
                                                       float *__restrict__ lam, float *__restrict__ bcen,
                                                       float *__restrict__ rcb) {
+    static_assert(DP == 64, "the operand layout below assumes 64 dimensions (8 chunks of 8)");
     constexpr int NB = kSweepBlock;
     constexpr float kInf = __builtin_inff();
     __shared__ float s_cb[DP];
-    __shared__ uint32_t s_max;
+    __shared__ uint32_t s_rmax[4];  // per leaf slot: largest row norm (bits)
+    __shared__ uint32_t s_max;      // the block: largest centre norm (bits)
     const int rb = blockIdx.x;
     const int tid = threadIdx.x;
-    const int li = tid >> 5, i = tid & 31;
+    const int ls = tid >> 8, t = tid & 255;
+    const int i = t >> 3, c = t & 7, h = c & 1, s = c >> 1;
     const int nl = a.r_first_leaf + 1;
     const int n_blocks = (nl + NB - 1) / NB;
     const int bnode = n_blocks - 1 + rb;  // heap index of the block's subtree node
     if (tid < DP) {
         const float *bx = a.rbox + int64_t(bnode) * 2 * DP;
-        const float c = 0.5f * (bx[tid] + bx[DP + tid]);
-        s_cb[tid] = c;
-        bcen[int64_t(rb) * DP + tid] = c;
+        const float cc = 0.5f * (bx[tid] + bx[DP + tid]);
+        s_cb[tid] = cc;
+        bcen[int64_t(rb) * DP + tid] = cc;
     }
+    if (tid < 4) s_rmax[tid] = 0u;
     if (tid == 0) s_max = 0u;
     __syncthreads();
-    const int L = rb * NB + li;
-    const bool leaf_ok = L < nl;
-    const int node = a.r_first_leaf + (leaf_ok ? L : 0);
-    const int cnt = leaf_ok ? a.rrange[node].y : 0;
-    const bool vr = i < cnt;
-    // row i: -2 (r - C_B) in BF16 at [h][s][e] for dimension 16 s + 8 h + e
-    {
-        const float *row = a.rlpts + (int64_t(L < nl ? L : 0) * a.r_leaf_slots + (vr ? i : 0)) * DP;
-        uint16_t *dst = abf + (int64_t(L) * NB + i) * DP;
-        float n2 = 0.f;
+    for (int l0 = 0; l0 < NB; l0 += 4) {
+        const int L = rb * NB + l0 + ls;
+        const bool leaf_ok = L < nl;
+        const int node = a.r_first_leaf + (leaf_ok ? L : 0);
+        const int cnt = leaf_ok ? a.rrange[node].y : 0;
+        const bool vr = i < cnt;
+        // row i, dimensions 8c .. 8c+7: -2 (r - C_B) in BF16 (one 16-byte store)
+        {
+            const float4 *src = reinterpret_cast<const float4 *>(
+                a.rlpts + (int64_t(leaf_ok ? L : 0) * a.r_leaf_slots + (vr ? i : 0)) * DP + 8 * c);
+            const float4 x0 = src[0], x1 = src[1];
+            const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+            bf16x8_t out;
+            float n2 = 0.f;
 #pragma unroll
-        for (int dd = 0; dd < DP; ++dd) {
-            const float df = vr ? row[dd] - s_cb[dd] : 0.f;
-            n2 = fmaf(df, df, n2);
-            const int s = dd >> 4, h = (dd >> 3) & 1, e = dd & 7;
-            dst[h * (DP / 2) + s * 8 + e] = __builtin_bit_cast(uint16_t, (__bf16)(-2.0f * df));
+            for (int e = 0; e < 8; ++e) {
+                const float df = vr ? xv[e] - s_cb[8 * c + e] : 0.f;
+                n2 = fmaf(df, df, n2);
+                out[e] = (__bf16)(-2.0f * df);
+            }
+            *reinterpret_cast<bf16x8_t *>(abf + (int64_t(L) * NB + i) * DP + h * (DP / 2) + s * 8) = out;
+            n2 = reduce8(n2, OpAdd());  // the row's whole norm, in all 8 lanes
+            if (c == 0) {
+                rn[int64_t(L) * NB + i] = vr ? n2 : kInf;
+                // non-negative floats order as unsigned integers
+                if (vr) atomicMax(&s_rmax[ls], __float_as_uint(n2));
+            }
         }
-        rn[int64_t(L) * NB + i] = vr ? n2 : kInf;
-        const float m = reduce32(vr ? n2 : 0.f, OpMax());
-        if (i == 0) rlen[L] = __builtin_amdgcn_sqrtf(m) * (1.0f + 0x1p-20f);
+        // the leaf's box centre C_L - C_B: the slot's first wave, lane = dimension
+        if (t < DP) {
+            const bool has = leaf_ok && cnt > 0;
+            const float *bx = a.rbox + int64_t(node) * 2 * DP;
+            const float df = has ? 0.5f * (bx[t] + bx[DP + t]) - s_cb[t] : 0.f;
+            const int ps = t >> 4, ph = (t >> 3) & 1, pe = t & 7;
+            cbf[int64_t(L) * DP + ph * (DP / 2) + ps * 8 + pe] =
+                __builtin_bit_cast(uint16_t, (__bf16)(-2.0f * df));
+            const float c2 = reduce64(df * df, OpAdd());
+            if (t == 0) {
+                cn[L] = has ? c2 : kInf;
+                lam[L] = has ? a.rlam[node] : 0.f;
+                if (has) atomicMax(&s_max, __float_as_uint(c2));
+            }
+        }
+        __syncthreads();
+        if (t == 0) {
+            rlen[L] = __builtin_amdgcn_sqrtf(__uint_as_float(s_rmax[ls])) * (1.0f + 0x1p-20f);
+            s_rmax[ls] = 0u;
+        }
+        __syncthreads();
     }
-    // the leaf's box centre C_L - C_B: this thread's dimensions i and i + 32
-    {
-        const bool has = leaf_ok && cnt > 0;
-        const float *bx = a.rbox + int64_t(node) * 2 * DP;
-        float c2 = 0.f;
-#pragma unroll
-        for (int u = 0; u < DP / 32; ++u) {
-            const int dd = i + 32 * u;
-            const float df = has ? 0.5f * (bx[dd] + bx[DP + dd]) - s_cb[dd] : 0.f;
-            c2 = fmaf(df, df, c2);
-            const int s = dd >> 4, h = (dd >> 3) & 1, e = dd & 7;
-            cbf[int64_t(L) * DP + h * (DP / 2) + s * 8 + e] = __builtin_bit_cast(uint16_t, (__bf16)(-2.0f * df));
-        }
-        c2 = reduce32(c2, OpAdd());
-        if (i == 0) {
-            cn[L] = has ? c2 : kInf;
-            lam[L] = has ? a.rlam[node] : 0.f;
-            // non-negative floats order as unsigned integers
-            if (has) atomicMax(&s_max, __float_as_uint(c2));
-        }
-    }
-    __syncthreads();
     if (tid == 0) rcb[rb] = __builtin_amdgcn_sqrtf(__uint_as_float(s_max)) * (1.0f + 0x1p-20f);
 }
 
