@@ -14,6 +14,8 @@ namespace {
 // block's subtree node, the same FP32 value the search reads back from bcen.
 // Norms are FP32 sums of the FP32 differences in a fixed order (chunk, then
 // a lane tree): the tile margin counts that error.
+constexpr int kMebSteps = 32;  // enclosing-ball steps per leaf
+
 template <int DP>
 __global__ __launch_bounds__(1024) void k_wsweep_prep(const SearchArgs a, uint16_t *__restrict__ abf,
                                                       float *__restrict__ rn, float *__restrict__ rlen,
@@ -24,6 +26,8 @@ __global__ __launch_bounds__(1024) void k_wsweep_prep(const SearchArgs a, uint16
     constexpr int NB = kSweepBlock;
     constexpr float kInf = __builtin_inff();
     __shared__ float s_cb[DP];
+    __shared__ __align__(16) float s_rows[4][32][DP];  // per leaf slot: its rows
+    __shared__ __align__(16) float s_c[4][DP];         // per leaf slot: the ball's centre
     __shared__ uint32_t s_rmax[4];  // per leaf slot: largest row norm (bits)
     __shared__ uint32_t s_max;      // the block: largest centre norm (bits)
     const int rb = blockIdx.x;
@@ -70,18 +74,56 @@ __global__ __launch_bounds__(1024) void k_wsweep_prep(const SearchArgs a, uint16
                 if (vr) atomicMax(&s_rmax[ls], __float_as_uint(n2));
             }
         }
-        // the leaf's box centre C_L - C_B: the slot's first wave, lane = dimension
+        // the leaf's ball for the block Score, a small enclosing ball: from
+        // the box centre, steps of Badoiu and Clarkson (move the centre 1/(i+1)
+        // of the way to the farthest point), keeping the centre whose largest
+        // distance was smallest; the radius is that largest distance (FP32,
+        // rounded up by 2^-12: far above the sum's rounding).  Then C_L - C_B.
+        // The slot's first wave: lane = dimension, or lane = row for the
+        // distances.
         if (t < DP) {
             const bool has = leaf_ok && cnt > 0;
             const float *bx = a.rbox + int64_t(node) * 2 * DP;
-            const float df = has ? 0.5f * (bx[t] + bx[DP + t]) - s_cb[t] : 0.f;
+            const float *rows = a.rlpts + int64_t(leaf_ok ? L : 0) * a.r_leaf_slots * DP;
+            for (int r = 0; r < cnt; ++r) s_rows[ls][r][t] = rows[r * DP + t];
+            float cl = has ? 0.5f * (bx[t] + bx[DP + t]) : 0.f;
+            float best_c = cl, best_r2 = kInf;
+            for (int it = 0; it < kMebSteps && has; ++it) {
+                s_c[ls][t] = cl;
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+                // lane r < cnt: squared distance of row r to the centre
+                float d2 = -1.0f;
+                if (t < cnt) {
+                    d2 = 0.f;
+#pragma unroll 4
+                    for (int u = 0; u < DP; u += 4) {
+                        const float4 x = *reinterpret_cast<const float4 *>(&s_rows[ls][t][u]);
+                        const float4 cc = *reinterpret_cast<const float4 *>(&s_c[ls][u]);
+                        const float g0 = x.x - cc.x, g1 = x.y - cc.y, g2 = x.z - cc.z, g3 = x.w - cc.w;
+                        d2 = fmaf(g0, g0, d2);
+                        d2 = fmaf(g1, g1, d2);
+                        d2 = fmaf(g2, g2, d2);
+                        d2 = fmaf(g3, g3, d2);
+                    }
+                }
+                const float m = __builtin_bit_cast(
+                    float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, reduce64(d2, OpMax()))));
+                if (m < best_r2) {
+                    best_r2 = m;
+                    best_c = cl;
+                }
+                const int f = __builtin_ctzll(ballot(d2 == m));
+                cl += (s_rows[ls][f][t] - cl) / float(it + 2);
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            }
+            const float df = has ? best_c - s_cb[t] : 0.f;
             const int ps = t >> 4, ph = (t >> 3) & 1, pe = t & 7;
             cbf[int64_t(L) * DP + ph * (DP / 2) + ps * 8 + pe] =
                 __builtin_bit_cast(uint16_t, (__bf16)(-2.0f * df));
             const float c2 = reduce64(df * df, OpAdd());
             if (t == 0) {
                 cn[L] = has ? c2 : kInf;
-                lam[L] = has ? a.rlam[node] : 0.f;
+                lam[L] = has ? __builtin_amdgcn_sqrtf(best_r2) * (1.0f + 0x1p-12f) : 0.f;
                 if (has) atomicMax(&s_max, __float_as_uint(c2));
             }
         }
