@@ -26,7 +26,9 @@ __global__ __launch_bounds__(1024) void k_wsweep_prep(const SearchArgs a, uint16
     constexpr int NB = kSweepBlock;
     constexpr float kInf = __builtin_inff();
     __shared__ float s_cb[DP];
-    __shared__ __align__(16) float s_rows[4][32][DP];  // per leaf slot: its rows
+    // per leaf slot: its rows (padded by 4 floats: a lane per row reads
+    // them without bank conflicts)
+    __shared__ __align__(16) float s_rows[4][32][DP + 4];
     __shared__ __align__(16) float s_c[4][DP];         // per leaf slot: the ball's centre
     __shared__ uint32_t s_rmax[4];  // per leaf slot: largest row norm (bits)
     __shared__ uint32_t s_max;      // the block: largest centre norm (bits)
@@ -113,7 +115,8 @@ __global__ __launch_bounds__(1024) void k_wsweep_prep(const SearchArgs a, uint16
                     best_c = cl;
                 }
                 const int f = __builtin_ctzll(ballot(d2 == m));
-                cl += (s_rows[ls][f][t] - cl) / float(it + 2);
+                // (any centre is valid: the step needs no exact division)
+                cl += (s_rows[ls][f][t] - cl) * __builtin_amdgcn_rcpf(float(it + 2));
                 asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
             }
             const float df = has ? best_c - s_cb[t] : 0.f;
