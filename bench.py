@@ -50,7 +50,7 @@ PEAKS = {  # MI355X published dense peaks
 # the counters were taken appear here.
 TRAFFIC_BYTES_PER_LAUNCH = {
     ("gmm1m_d3_k10", "fp32"): int((342779.5 * 2.000 + 158830.5625 * 1.000) * 1024),
-    ("manifold1m_d64_k50", "bf16"): int((212598381.75 * 2.000 + 282790.75 * 1.000) * 1024),
+    ("manifold1m_d64_k50", "bf16"): int((182753836.3125 * 2.000 + 265397.375 * 1.000) * 1024),
 }
 
 COMBINED_WORKLOAD = "manifold1m_d64_k50"
