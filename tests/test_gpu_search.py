@@ -164,6 +164,21 @@ def test_bf16_dims_and_self(d, k):
     _check(ref, q, k, gi, gd)
 
 
+@pytest.mark.parametrize("d,k,leaf", [(12, 5, 20), (30, 4, 24), (17, 11, 9), (32, 16, 32)])
+def test_bf16_matrix_core_traversal_shapes(d, k, leaf):
+    """The traversal kernel with matrix-core tiles (stride 16 or 32, lists of
+    <= 16) at leaf sizes below 32 (rows past the leaf, idle lanes of a half)
+    and every list length it instantiates, in query and self mode."""
+    rng = np.random.default_rng(d * 1000 + k * 10 + leaf)
+    basis = rng.standard_normal((5, d))
+    ref = (rng.random((6000, 5)) @ basis + 0.03 * rng.standard_normal((6000, d))).astype(np.float32)
+    q = (rng.random((900, 5)) @ basis + 0.03 * rng.standard_normal((900, d))).astype(np.float32)
+    gi, gd, _ = _search(ref, q, k, leaf, precision="bf16")
+    _check(ref, q, k, gi, gd)
+    gi, gd, _ = _search(ref, None, k, leaf, precision="bf16")
+    _check(ref, None, k, gi, gd)
+
+
 @pytest.mark.parametrize("n_ref,n_q,k,leaf", [(20, 5, 7, 32), (700, 5, 7, 32), (700, 70, 3, 16),
                                              (3000, 200, 50, 32)])
 def test_bf16_sweep_small_and_idle_waves(n_ref, n_q, k, leaf):

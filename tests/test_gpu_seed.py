@@ -174,6 +174,29 @@ def test_any_seed_per_leaf_bf16_kernel(kind):
         assert st["fallback_leaves"] == nl // 2
 
 
+@pytest.mark.parametrize("kind", ["zero", "half", "quarter", "random"])
+def test_any_seed_matrix_core_traversal_stride32(kind):
+    """Stride 32 with lists of 10: the matrix-core traversal's second pass in
+    the same wave, for any seed, against the oracle and the plain search."""
+    rng = np.random.default_rng(28)
+    basis = rng.standard_normal((6, 28))
+    ref = (rng.random((12000, 6)) @ basis + 0.05 * rng.standard_normal((12000, 28))).astype(np.float32)
+    q = (rng.random((1500, 6)) @ basis + 0.05 * rng.standard_normal((1500, 28))).astype(np.float32)
+    k, leaf = 10, 32
+    plain = _seeded(ref, q, k, leaf, lambda n: None, "bf16")
+    got = _seeded(ref, q, k, leaf, _seed_fn(kind, plain[1]), "bf16")
+    oi, od = ok.knn(q, ref, k)
+    parity.assert_ok(q, ref, k, got[0], got[1], oi, od)
+    assert np.array_equal(got[0], plain[0]) and np.array_equal(got[1], plain[1])
+    st, nl = got[2], got[2]["n_query_leaves"]
+    if kind == "zero":
+        assert st["fallback_leaves"] == nl
+    elif kind == "half":
+        assert st["fallback_leaves"] == nl // 2
+    elif kind == "quarter":
+        assert st["fallback_leaves"] == nl // 4
+
+
 def test_trained_seed_prunes_more_and_stays_exact():
     """Train on 8 seeded draws of the Zipf-GMM workload (scaled down), then
     on a held-out draw: the seeded search returns the oracle's answer with
