@@ -71,7 +71,7 @@ def parse():
                     help="train the seed network on 8 other seeded draws of the workload "
                          "(untimed), then time steps that include seed inference")
     ap.add_argument("--train-epochs", type=int, default=20)
-    ap.add_argument("--target-fallback", type=float, default=0.0005,
+    ap.add_argument("--target-fallback", type=float, default=0.005,
                     help="seed calibration: share of held-out leaves allowed above the seed")
     ap.add_argument("--compare", action="store_true",
                     help="also time the plain FP32 path on the same workload and report "
