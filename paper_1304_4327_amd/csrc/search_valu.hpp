@@ -720,10 +720,12 @@ __device__ __forceinline__ void search_valu_body(const SearchArgs &a) {
     }
 }
 
-// d = 8 with short lists: seven waves per SIMD fit (one register fewer than
-// the compiler's own choice, which allows six)
+// Short lists: at d = 8 seven waves per SIMD fit (one register fewer than
+// the compiler's own choice, which allows six), at d = 16 six (instead of
+// five, with a few spills)
 template <int D, int K, int LG, int MODE = kValuPlain>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 8 && K <= 16 ? 7 : 1))) void
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    D == 8 && K <= 16 ? 7 : D == 16 && K <= 16 ? 6 : 1))) void
 k_search_valu(const SearchArgs a) {
     search_valu_body<D, K, LG, MODE, false>(a);
 }
