@@ -720,12 +720,13 @@ __device__ __forceinline__ void search_valu_body(const SearchArgs &a) {
     }
 }
 
-// Short lists: at d = 8 seven waves per SIMD fit (one register fewer than
-// the compiler's own choice, which allows six), at d = 16 six (instead of
-// five, with a few spills)
+// Plain form with short lists: at d = 8 seven waves per SIMD fit (one
+// register fewer than the compiler's own choice, which allows six), at
+// d = 16 six (instead of five, with a few spills); the seeded form carries
+// more state and keeps the compiler's choice
 template <int D, int K, int LG, int MODE = kValuPlain>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    D == 8 && K <= 16 ? 7 : D == 16 && K <= 16 ? 6 : 1))) void
+    MODE != kValuPlain || K > 16 ? 1 : D == 8 ? 7 : D == 16 ? 6 : 1))) void
 k_search_valu(const SearchArgs a) {
     search_valu_body<D, K, LG, MODE, false>(a);
 }
