@@ -39,8 +39,10 @@
 
 namespace knnx {
 
+// low dimension, short lists: six waves per SIMD fit without spills
 template <int DP, int K, int LG>
-__global__ __launch_bounds__(256) void k_search_far(const SearchArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DP <= 4 && K <= 16 ? 6 : 1))) void
+k_search_far(const SearchArgs a) {
     constexpr float kInf = __builtin_inff();
     constexpr float kShrink = 1.0f - 0x1p-16f;            // prune slack (squared)
     constexpr float kGamma = 1.0f - (DP + 6) * 0x1p-24f;  // FP32 filter slack
